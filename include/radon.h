@@ -1,0 +1,166 @@
+/*
+ * radon.h - C ABI of the MI355X (gfx950) Radon NUFFT library.
+ *
+ * The library applies the 2D Radon transform and its exact adjoint through
+ * the Fourier slice theorem, as in Maia et al., "Compressive Phase Contrast
+ * Tomography", section "fast radon transform": a 2D FFT of the image on a
+ * regular (oversampled) grid, interpolation of that transform onto a polar
+ * grid by gridding with a Kaiser-Bessel kernel, and 1D inverse FFTs along
+ * every radial line; the adjoint ("inverse gridding" in the abstract) runs
+ * the steps in reverse with a deterministic, binned spreading step (no
+ * floating-point atomics). The solver of the paper's L1 problem (section
+ * "INTRODUCTION", displayed problem) needs exactly these two maps.
+ *
+ * Conventions (all calls):
+ *   image    n x n float32, row-major; pixel (i, j) is the point
+ *            (px, py) = (j - n/2, i - n/2), unit spacing.
+ *   sinogram n_views x n_det float32, row-major; bin d is the detector
+ *            offset s = d - n_det/2; view a has direction
+ *            (cos angles[a], sin angles[a]); angle 0 projects along y.
+ *   forward  y[a,d] = Re((1/N) sum_q X~_a[q] exp(2 pi i q s_d / N)), where
+ *            X~_a[q] is the Kaiser-Bessel gridding estimate of the image's
+ *            Fourier transform at k = (q/N)(cos, sin), q = -N/2..N/2-1.
+ *   adjoint  exact transpose of the forward in the real inner product
+ *            (no ramp filter, no 1/n_views scaling).
+ *   Device pointers are plain HIP device addresses of the device that was
+ *   current when the plan was made; that device must be current for every
+ *   call on the plan. `stream` is a hipStream_t (NULL = default stream).
+ *   Calls enqueue work on the stream and never synchronise the host.
+ *   Inputs are never modified; outputs are fully overwritten; input and
+ *   output must not overlap.
+ *
+ * Errors: nothing aborts or throws across this interface. Argument errors
+ * return synchronously before any launch; launch failures return
+ * RADON_ERR_DEVICE; asynchronous device faults surface at the caller's next
+ * synchronisation. radon_last_error() gives a thread-local message.
+ *
+ * Thread safety: a plan owns one workspace, so one plan may be used by one
+ * stream at a time. Distinct plans are independent.
+ */
+#ifndef RADON_H
+#define RADON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct radon_plan_s* radon_plan_t;
+
+typedef enum {
+    RADON_OK = 0,
+    RADON_ERR_INVALID = 1,      /* bad argument (NULL pointer, bad size)          */
+    RADON_ERR_UNSUPPORTED = 2,  /* valid but outside what the kernels implement   */
+    RADON_ERR_OOM = 3,          /* device allocation failed                       */
+    RADON_ERR_DEVICE = 4        /* HIP runtime or launch error                    */
+} radon_status_t;
+
+/*
+ * Build a plan for n x n images, n_views angles (host array of float64
+ * radians, any order, copied) and n_det detector bins, oversampling sigma and
+ * Kaiser-Bessel width W (section "fast radon transform", paragraphs 1-4).
+ *
+ * Requirements: n and n_det even and >= 8; sigma * n an integer equal to
+ * 2 n (only sigma = 2 is implemented: RADON_ERR_UNSUPPORTED otherwise);
+ * W in {4, 6, 8}; n and n_det in the supported FFT lengths (2^a 3^b 5^c,
+ * listed by radon_supported_length); n_views >= 1.
+ *
+ * The plan computes per-view cos/sin in float64 on the host, builds the
+ * Kaiser-Bessel table and deapodization factors in float64 (rounded once
+ * to float32), sorts the polar samples by footprint tile on the device, and
+ * allocates its workspace. It synchronises the device before returning.
+ * On failure *out is set to NULL. Release with radon_plan_destroy.
+ */
+radon_status_t radon_plan(radon_plan_t* out, int n, const double* angles, int n_views,
+                          int n_det, double sigma, int W);
+
+/* Forward Radon transform: img_dev (n*n float32) -> sino_dev (n_views*n_det float32). */
+radon_status_t radon_forward(radon_plan_t plan, const float* img_dev, float* sino_dev,
+                             void* stream);
+
+/* Adjoint Radon transform: sino_dev (n_views*n_det float32) -> img_dev (n*n float32). */
+radon_status_t radon_adjoint(radon_plan_t plan, const float* sino_dev, float* img_dev,
+                             void* stream);
+
+/* batch slices that share the plan's geometry, back to back on the stream:
+ * imgs_dev is batch*n*n float32, sinos_dev is batch*n_views*n_det float32. */
+radon_status_t radon_forward_batched(radon_plan_t plan, int batch, const float* imgs_dev,
+                                     float* sinos_dev, void* stream);
+radon_status_t radon_adjoint_batched(radon_plan_t plan, int batch, const float* sinos_dev,
+                                     float* imgs_dev, void* stream);
+
+/*
+ * Test hook: copy the plan's stable sample sort to host memory. The sorted
+ * samples are the n_views*n_det polar samples j = a*n_det + q + n_det/2
+ * followed by n_views mirrored Nyquist samples (view a at q = +n_det/2).
+ * Keys are the footprint-origin tile (section "fast radon transform",
+ * paragraph 4, read as uniform tiles): o = (floor(u) - W/2 + 1 + G/2) mod G,
+ * key = (o_v div T)*(G/T) + (o_u div T). perm gets the sorted sample ids
+ * (perm_cap >= n_samples), offsets the n_bins+1 bin starts. Either pointer
+ * may be NULL. Sizes come from radon_plan_info.
+ */
+radon_status_t radon_plan_sort_indices(radon_plan_t plan, int32_t* perm_host, int64_t perm_cap,
+                                       int32_t* offsets_host, int64_t offsets_cap);
+
+/*
+ * Plan facts for tests and benchmarks. info[k] (k < cap) receives:
+ *  0 n, 1 n_views, 2 n_det, 3 W, 4 G, 5 tile T, 6 sorted samples,
+ *  7 bins, 8 spreading work items, 9 partial slots, 10 device bytes.
+ */
+radon_status_t radon_plan_info(radon_plan_t plan, int64_t* info, int cap);
+
+/* Device memory owned by the plan, in bytes (0 for NULL). */
+size_t radon_plan_device_bytes(radon_plan_t plan);
+
+/* Free the plan and its device memory. NULL-safe. Synchronises the device. */
+void radon_plan_destroy(radon_plan_t plan);
+
+/* 1 if len is a supported FFT length (image size or detector count), else 0. */
+int radon_supported_length(int len);
+
+/* Static name of a status code. */
+const char* radon_status_string(radon_status_t status);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* radon_last_error(void);
+
+/*
+ * Stage timing. With profiling on, every kernel launch of forward/adjoint is
+ * bracketed by HIP events on the caller's stream; radon_plan_stage_times
+ * synchronises on those events and returns, per stage, the accumulated
+ * milliseconds and launch counts since profiling was switched on. Stage names
+ * come from radon_stage_name(0 .. radon_stage_count()-1).
+ */
+radon_status_t radon_plan_set_profiling(radon_plan_t plan, int enable);
+radon_status_t radon_plan_stage_times(radon_plan_t plan, double* ms, int64_t* counts, int cap);
+int radon_stage_count(void);
+const char* radon_stage_name(int stage);
+
+/*
+ * Test hooks that run parts of the path on the plan's workspace.
+ * radon_debug_forward_grid: deapodize + zero-pad + 2D FFT of img_dev, then
+ *   copy the half-plane grid to grid_dev: (G/2+1) x G complex64, element
+ *   [mx][my] = Ghat at frequency (mx, my) (transposed: mx major).
+ * radon_debug_adjoint_grid: ray FFTs + binned spreading of sino_dev, copy the
+ *   Hermitian part of the spread grid, same layout, to grid_dev.
+ */
+radon_status_t radon_debug_forward_grid(radon_plan_t plan, const float* img_dev, float* grid_dev,
+                                        void* stream);
+radon_status_t radon_debug_adjoint_grid(radon_plan_t plan, const float* sino_dev, float* grid_dev,
+                                        void* stream);
+
+/*
+ * Test hook for the batched LDS FFT: `batch` independent complex64 lines of
+ * length len (in_dev, out_dev: batch*len complex64, may not alias), forward
+ * (exp(-), inverse = 0) or unnormalised inverse (exp(+), inverse = 1).
+ */
+radon_status_t radon_fft_test(int len, int batch, int inverse, const float* in_dev,
+                              float* out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADON_H */

@@ -1,0 +1,201 @@
+// fft_lds.hpp - batched complex64 FFTs resident in LDS, for gfx950.
+//
+// Every 1D transform of the Radon path (the oversampled 2D FFT done as row
+// and column passes, and the ray FFTs; section "fast radon transform",
+// paragraph 1) runs on this engine: a Stockham autosort FFT of compile-time
+// length LEN = 2^a 3^b 5^c, radix 8/4/2/3/5 passes, all lines of a workgroup
+// transformed together. Each pass reads its butterflies' inputs from LDS into
+// registers, barriers, applies twiddles and the radix-R DFT, writes the
+// outputs back in place, and barriers again; no scratch buffer is needed.
+// Twiddles come from a float32 table e^{-2 pi i t/LEN}, t < LEN, built in
+// float64 on the host. The engine computes the forward (e^-) transform; the
+// callers obtain inverse transforms as conj(FFT(conj(x))).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rn {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// -i * a and +i * a
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+__device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }
+
+// ---- radix-R forward DFT kernels (y_k = sum_m v_m e^{-2 pi i m k / R})
+
+template <int R> struct Dft;
+
+template <> struct Dft<2> {
+    static __device__ __forceinline__ void run(float2* v) {
+        float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <> struct Dft<3> {
+    static __device__ __forceinline__ void run(float2* v) {
+        const float s3 = 0.86602540378443865f;  // sin(2 pi / 3)
+        float2 t = cadd(v[1], v[2]);
+        float2 d = csub(v[1], v[2]);
+        float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
+        float2 r = mul_mi(cscale(d, s3));       // -i s3 (v1 - v2)
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, r);
+        v[2] = csub(m, r);
+    }
+};
+
+template <> struct Dft<4> {
+    static __device__ __forceinline__ void run(float2* v) {
+        float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        float2 t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    }
+};
+
+template <> struct Dft<5> {
+    static __device__ __forceinline__ void run(float2* v) {
+        const float c1 = 0.30901699437494742f;   // cos(2 pi / 5)
+        const float c2 = -0.80901699437494742f;  // cos(4 pi / 5)
+        const float s1 = 0.95105651629515357f;   // sin(2 pi / 5)
+        const float s2 = 0.58778525229247313f;   // sin(4 pi / 5)
+        float2 t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+        float2 t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+        float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+        float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+        float2 b1 = mul_mi(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+        float2 b2 = mul_mi(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+        v[0] = cadd(v[0], cadd(t1, t2));
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
+    }
+};
+
+template <> struct Dft<8> {
+    static __device__ __forceinline__ void run(float2* v) {
+        const float h = 0.70710678118654752f;
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4>::run(e);
+        Dft<4>::run(o);
+        // o_k *= e^{-i pi k / 4}
+        float2 o1 = make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+        float2 o2 = mul_mi(o[2]);
+        float2 o3 = make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    }
+};
+
+// ---- compile-time radix plan: 5s, then 3s, then the power of two as 8s
+// (a leftover 2^1 or 2^2 becomes 4x4 or 4 when there are enough factors).
+
+struct RadixPlan {
+    int np;
+    int r[24];
+};
+
+constexpr RadixPlan make_plan(int len) {
+    RadixPlan p{0, {}};
+    while (len % 5 == 0) { p.r[p.np++] = 5; len /= 5; }
+    while (len % 3 == 0) { p.r[p.np++] = 3; len /= 3; }
+    int k = 0;
+    while (len % 2 == 0) { ++k; len /= 2; }
+    int e8 = k / 3, rem = k % 3;
+    if (rem == 1 && e8 >= 1) { --e8; for (int i = 0; i < e8; ++i) p.r[p.np++] = 8; p.r[p.np++] = 4; p.r[p.np++] = 4; }
+    else {
+        for (int i = 0; i < e8; ++i) p.r[p.np++] = 8;
+        if (rem == 1) p.r[p.np++] = 2;
+        if (rem == 2) p.r[p.np++] = 4;
+    }
+    if (len != 1) p.np = -1;  // unsupported factor
+    return p;
+}
+
+constexpr bool length_ok(int len) { return len >= 2 && make_plan(len).np > 0; }
+
+// One Stockham pass of radix R over B lines (line b at buf + b*LS), sub-length L.
+template <int LEN, int R, int L, int B, int NT, int LS>
+__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw, int tid) {
+    constexpr int NB = LEN / R;                 // butterflies per line
+    constexpr int TOT = NB * B;
+    constexpr int IT = (TOT + NT - 1) / NT;
+    constexpr bool FULL = (TOT % NT) == 0;
+    float2 v[IT][R];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = tid + it * NT;
+        if (FULL || b < TOT) {
+            const int line = b / NB;
+            const int bf = b - line * NB;
+            const float2* src = buf + line * LS + bf;
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[it][m] = src[m * NB];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int b = tid + it * NT;
+        if (FULL || b < TOT) {
+            const int line = b / NB;
+            const int bf = b - line * NB;
+            const int j = bf % L;
+            const int k = bf / L;
+            if constexpr (L > 1) {
+                constexpr int STEP = LEN / (L * R);
+#pragma unroll
+                for (int m = 1; m < R; ++m) v[it][m] = cmul(v[it][m], tw[j * m * STEP]);
+            }
+            Dft<R>::run(v[it]);
+            float2* dst = buf + line * LS + k * (L * R) + j;
+#pragma unroll
+            for (int m = 0; m < R; ++m) dst[m * L] = v[it][m];
+        }
+    }
+    __syncthreads();
+}
+
+template <int LEN, int P, int L, int B, int NT, int LS>
+__device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict__ tw, int tid) {
+    constexpr RadixPlan plan = make_plan(LEN);
+    if constexpr (P < plan.np) {
+        constexpr int R = plan.r[P];
+        stockham_pass<LEN, R, L, B, NT, LS>(buf, tw, tid);
+        fft_passes<LEN, P + 1, L * R, B, NT, LS>(buf, tw, tid);
+    }
+}
+
+// Forward FFT of B lines of length LEN in LDS (line b at buf + b*LS).
+// All NT threads of the workgroup must call it; the caller barriers before.
+template <int LEN, int B, int NT, int LS = LEN>
+__device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw, int tid) {
+    static_assert(length_ok(LEN), "FFT length must be 2^a 3^b 5^c");
+    fft_passes<LEN, 0, 1, B, NT, LS>(buf, tw, tid);
+}
+
+// Threads per workgroup used for a transform of B lines of length LEN.
+constexpr int fft_threads(int len, int b) {
+    int work = len * b / 8;
+    return work >= 256 ? 256 : (work >= 128 ? 128 : 64);
+}
+
+}  // namespace rn

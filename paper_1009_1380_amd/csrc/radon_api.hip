@@ -1,0 +1,609 @@
+// radon_api.hip - the C ABI (include/radon.h): plan construction on the host
+// (float64 geometry and tables), the device sample sort, and the enqueueing of
+// the forward and adjoint kernel sequences on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/radon.h"
+#include "radon_internal.hpp"
+#include "radon_sort.hpp"
+
+using rn::Plan;
+
+struct radon_plan_s {
+    Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+radon_status_t fail(radon_status_t st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+radon_status_t ok() {
+    g_last_error.clear();
+    return RADON_OK;
+}
+
+// Visits per spreading work item; longer tile lists are split and their
+// partial tiles summed in a fixed order.
+constexpr int kA2Chunk = 512;
+// Kaiser-Bessel table entries per unit of t.
+constexpr int kKbL = 1024;
+
+// I0(x) by its power series sum ((x/2)^(2k) / (k!)^2); x <= 40 here.
+double bessel_i0(double x) {
+    const double y = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= y / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+// phi(t) = I0(beta sqrt(1 - (2t/W)^2)) / I0(beta) on |t| < W/2.
+double kb_phi(double t, int W, double beta) {
+    const double r = 2.0 * t / W;
+    if (fabs(r) >= 1.0) return 0.0;
+    return bessel_i0(beta * sqrt(1.0 - r * r)) / bessel_i0(beta);
+}
+
+// Fourier transform of phi: (W / I0(beta)) sinh(z)/z, z^2 = beta^2 - (pi W f)^2.
+double kb_phihat(double f, int W, double beta) {
+    const double z2 = beta * beta - (M_PI * W * f) * (M_PI * W * f);
+    double r;
+    if (z2 > 0) { const double z = sqrt(z2); r = sinh(z) / z; }
+    else if (z2 < 0) { const double z = sqrt(-z2); r = sin(z) / z; }
+    else r = 1.0;
+    return r * W / bessel_i0(beta);
+}
+
+bool is_supported_length(int len) { return rn::length_supported(len); }
+
+template <class T>
+radon_status_t dev_alloc(Plan& p, T** out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void* ptr = nullptr;
+    const size_t bytes = count * sizeof(T);
+    if (hipMalloc(&ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RADON_ERR_OOM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    p.allocs.push_back(ptr);
+    p.bytes += bytes;
+    *out = static_cast<T*>(ptr);
+    return RADON_OK;
+}
+
+template <class T>
+radon_status_t upload(T* dst, const std::vector<T>& src) {
+    if (hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RADON_ERR_DEVICE, "host-to-device copy failed");
+    }
+    return RADON_OK;
+}
+
+void free_plan(Plan& p) {
+    for (void* ptr : p.allocs) (void)hipFree(ptr);
+    p.allocs.clear();
+    for (auto& pt : p.pending) { (void)hipEventDestroy(pt.e0); (void)hipEventDestroy(pt.e1); }
+    p.pending.clear();
+    for (hipEvent_t e : p.event_pool) (void)hipEventDestroy(e);
+    p.event_pool.clear();
+}
+
+std::vector<float2> twiddles(int len) {
+    std::vector<float2> t(len);
+    for (int k = 0; k < len; ++k) {
+        const double a = -2.0 * M_PI * (double)k / (double)len;
+        t[k] = make_float2((float)cos(a), (float)sin(a));
+    }
+    return t;
+}
+
+hipEvent_t take_event(Plan& p) {
+    if (!p.event_pool.empty()) {
+        hipEvent_t e = p.event_pool.back();
+        p.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    return e;
+}
+
+// Run one launcher, bracketed by events when profiling is on.
+template <class F>
+hipError_t staged(Plan& p, int stage, hipStream_t st, F&& launch) {
+    if (!p.profiling) return launch();
+    hipEvent_t e0 = take_event(p), e1 = take_event(p);
+    if (!e0 || !e1) return launch();
+    (void)hipEventRecord(e0, st);
+    const hipError_t err = launch();
+    (void)hipEventRecord(e1, st);
+    p.pending.push_back({stage, e0, e1});
+    return err;
+}
+
+radon_status_t check_plan(radon_plan_t plan) {
+    if (!plan) return fail(RADON_ERR_INVALID, "plan is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RADON_ERR_DEVICE, "hipGetDevice failed");
+    }
+    if (dev != plan->p.device)
+        return fail(RADON_ERR_INVALID, "current device %d differs from the plan's device %d", dev,
+                    plan->p.device);
+    return RADON_OK;
+}
+
+radon_status_t launch_status(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(RADON_ERR_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+    return RADON_OK;
+}
+
+radon_status_t run_forward(Plan& p, const float* img, float* sino, hipStream_t st) {
+    radon_status_t s;
+    if ((s = launch_status(staged(p, rn::ST_F1, st, [&] { return rn::launch_f1(p, img, st); }), "F1"))) return s;
+    if ((s = launch_status(staged(p, rn::ST_F2, st, [&] { return rn::launch_f2(p, st); }), "F2"))) return s;
+    if ((s = launch_status(staged(p, rn::ST_F34, st, [&] { return rn::launch_f34(p, sino, st); }), "F34"))) return s;
+    return RADON_OK;
+}
+
+radon_status_t run_adjoint_grid(Plan& p, const float* sino, hipStream_t st) {
+    radon_status_t s;
+    if ((s = launch_status(staged(p, rn::ST_A1, st, [&] { return rn::launch_a1(p, sino, st); }), "A1"))) return s;
+    if ((s = launch_status(staged(p, rn::ST_A2, st, [&] { return rn::launch_a2(p, st); }), "A2"))) return s;
+    if (p.n_splits > 0)
+        if ((s = launch_status(staged(p, rn::ST_A2R, st, [&] { return rn::launch_a2_reduce(p, st); }), "A2 reduce"))) return s;
+    return RADON_OK;
+}
+
+radon_status_t run_adjoint(Plan& p, const float* sino, float* img, hipStream_t st) {
+    radon_status_t s;
+    if ((s = run_adjoint_grid(p, sino, st))) return s;
+    if ((s = launch_status(staged(p, rn::ST_A3, st, [&] { return rn::launch_a3(p, st); }), "A3"))) return s;
+    if ((s = launch_status(staged(p, rn::ST_A4, st, [&] { return rn::launch_a4(p, img, st); }), "A4"))) return s;
+    return RADON_OK;
+}
+
+// Device sort of the sample keys: keys, LSD radix passes, bin offsets.
+radon_status_t sort_samples(Plan& p, std::vector<int>& offsets_host) {
+    const int total = (int)p.n_samples;
+    const int nblocks = (total + rn::SORT_TILE - 1) / rn::SORT_TILE;
+    int *k0 = nullptr, *k1 = nullptr, *v0 = nullptr, *v1 = nullptr, *hist = nullptr;
+    auto cleanup = [&] {
+        for (int* x : {k0, k1, v0, v1, hist})
+            if (x) (void)hipFree(x);
+    };
+    if (hipMalloc(&k0, sizeof(int) * total) != hipSuccess || hipMalloc(&k1, sizeof(int) * total) != hipSuccess ||
+        hipMalloc(&v0, sizeof(int) * total) != hipSuccess || hipMalloc(&v1, sizeof(int) * total) != hipSuccess ||
+        hipMalloc(&hist, sizeof(int) * rn::SORT_RADIX * nblocks) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(RADON_ERR_OOM, "sort scratch allocation failed");
+    }
+    hipLaunchKernelGGL(rn::k_sample_keys, dim3((total + 255) / 256), dim3(256), 0, 0, p.cs, k0, v0,
+                       p.n_views, p.n_det, p.G, p.W, p.T);
+    int bits = 0;
+    while ((1 << bits) < p.n_bins) ++bits;
+    for (int shift = 0; shift < bits; shift += 4) {
+        hipLaunchKernelGGL(rn::k_sort_hist, dim3(nblocks), dim3(rn::SORT_NT), 0, 0, k0, total, shift, hist, nblocks);
+        hipLaunchKernelGGL(rn::k_exclusive_scan, dim3(1), dim3(1024), 0, 0, hist, rn::SORT_RADIX * nblocks);
+        hipLaunchKernelGGL(rn::k_sort_scatter, dim3(nblocks), dim3(rn::SORT_NT), 0, 0, k0, v0, k1, v1, total,
+                           shift, hist, nblocks);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    hipLaunchKernelGGL(rn::k_bin_offsets, dim3((p.n_bins + 1 + 255) / 256), dim3(256), 0, 0, k0, total,
+                       p.offsets, p.n_bins);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(p.perm, v0, sizeof(int) * total, hipMemcpyDeviceToDevice);
+    offsets_host.assign(p.n_bins + 1, 0);
+    if (e == hipSuccess)
+        e = hipMemcpy(offsets_host.data(), p.offsets, sizeof(int) * (p.n_bins + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    cleanup();
+    if (e != hipSuccess) return fail(RADON_ERR_DEVICE, "sample sort failed: %s", hipGetErrorString(e));
+    return RADON_OK;
+}
+
+// Spreading work list: one item per visit chunk of each half-plane output
+// tile (tile column 0 holds the mx = G/2 line, columns ntl/2..ntl-1 hold
+// mx = 0..G/2-1).
+radon_status_t build_work(Plan& p, const std::vector<int>& offs) {
+    const int ntl = p.ntl;
+    auto count = [&](int b) { return offs[b + 1] - offs[b]; };
+    std::vector<int> cols;
+    cols.push_back(0);
+    for (int cx = ntl / 2; cx < ntl; ++cx) cols.push_back(cx);
+    std::vector<rn::WorkItem> items;
+    std::vector<rn::SplitTile> splits;
+    int slots = 0;
+    for (int cy = 0; cy < ntl; ++cy) {
+        for (int cx : cols) {
+            const int xl = (cx + ntl - 1) % ntl, yu = (cy + ntl - 1) % ntl;
+            const int total = count(yu * ntl + xl) + count(yu * ntl + cx) + count(cy * ntl + xl) +
+                              count(cy * ntl + cx);
+            if (total <= kA2Chunk) {
+                items.push_back({cx, cy, 0, total, -1, 0, 0, 0});
+            } else {
+                const int nch = (total + kA2Chunk - 1) / kA2Chunk;
+                splits.push_back({cx, cy, slots, nch});
+                for (int k = 0; k < nch; ++k)
+                    items.push_back({cx, cy, k * kA2Chunk, std::min(kA2Chunk, total - k * kA2Chunk), slots + k,
+                                     0, 0, 0});
+                slots += nch;
+            }
+        }
+    }
+    // longest items first so the tail of the launch is short
+    std::stable_sort(items.begin(), items.end(),
+                     [](const rn::WorkItem& a, const rn::WorkItem& b) { return a.count > b.count; });
+    p.n_items = (int)items.size();
+    p.n_splits = (int)splits.size();
+    p.n_slots = slots;
+    radon_status_t s;
+    if ((s = dev_alloc(p, &p.items, items.size()))) return s;
+    if ((s = upload(p.items, items))) return s;
+    if ((s = dev_alloc(p, &p.splits, splits.size()))) return s;
+    if (!splits.empty() && (s = upload(p.splits, splits))) return s;
+    if ((s = dev_alloc(p, &p.partials, (size_t)std::max(slots, 1) * p.T * p.T))) return s;
+    return RADON_OK;
+}
+
+radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int n_det, double sigma, int W) {
+    p.n = n;
+    p.n_views = n_views;
+    p.n_det = n_det;
+    p.W = W;
+    p.sigma = sigma;
+    p.G = 2 * n;
+    const int G = p.G;
+    // tile size: largest of 32/16/8 dividing G/2 (so tiles do not straddle the
+    // half-plane edge) and at least W (a footprint spans at most two tiles)
+    p.T = 0;
+    for (int T : {32, 16, 8})
+        if ((G / 2) % T == 0 && T >= W) { p.T = T; break; }
+    if (p.T == 0) return fail(RADON_ERR_UNSUPPORTED, "no tile size in {8,16,32} fits G=%d", G);
+    p.ntl = G / p.T;
+    p.n_bins = p.ntl * p.ntl;
+    p.n_samples = (int64_t)n_views * n_det + n_views;
+    p.beta = M_PI * sqrt((W / sigma) * (W / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
+    p.kbL = (float)kKbL;
+
+    // host tables in float64, rounded once
+    std::vector<double2> cs(n_views);
+    for (int a = 0; a < n_views; ++a) cs[a] = make_double2(cos(angles[a]), sin(angles[a]));
+    std::vector<float> psi_inv(n);
+    for (int i = 0; i < n; ++i) psi_inv[i] = (float)(1.0 / kb_phihat(((double)i - n / 2) / G, W, p.beta));
+    std::vector<float2> shift(n);
+    for (int i = 0; i < n; ++i) {
+        const double a = -M_PI * ((double)i - n / 2) / (double)n;
+        shift[i] = make_float2((float)cos(a), (float)sin(a));
+    }
+    const int ntab = (W / 2) * kKbL;
+    std::vector<double> phi(ntab + 1);
+    for (int i = 0; i < ntab; ++i) phi[i] = kb_phi((double)i / kKbL, W, p.beta);
+    phi[ntab] = 1.0 / bessel_i0(p.beta);   // limit from inside the support
+    std::vector<float2> kb(ntab + 1);
+    for (int i = 0; i < ntab; ++i) kb[i] = make_float2((float)phi[i], (float)(phi[i + 1] - phi[i]));
+    kb[ntab] = make_float2((float)phi[ntab], 0.f);
+
+    radon_status_t s;
+    if ((s = dev_alloc(p, &p.cs, n_views)) || (s = upload(p.cs, cs))) return s;
+    if ((s = dev_alloc(p, &p.psi_inv, n)) || (s = upload(p.psi_inv, psi_inv))) return s;
+    if ((s = dev_alloc(p, &p.shift_n, n)) || (s = upload(p.shift_n, shift))) return s;
+    if ((s = dev_alloc(p, &p.tw_n, n)) || (s = upload(p.tw_n, twiddles(n)))) return s;
+    if ((s = dev_alloc(p, &p.tw_N, n_det)) || (s = upload(p.tw_N, twiddles(n_det)))) return s;
+    if ((s = dev_alloc(p, &p.kbtab, kb.size())) || (s = upload(p.kbtab, kb))) return s;
+    if ((s = dev_alloc(p, &p.perm, (size_t)p.n_samples))) return s;
+    if ((s = dev_alloc(p, &p.offsets, (size_t)p.n_bins + 1))) return s;
+    std::vector<int> offs;
+    if ((s = sort_samples(p, offs))) return s;
+    if ((s = build_work(p, offs))) return s;
+    if ((s = dev_alloc(p, &p.T1, (size_t)(n + 1) * n))) return s;
+    if ((s = dev_alloc(p, &p.grid, (size_t)(n + 1) * G))) return s;
+    if ((s = dev_alloc(p, &p.Yh, (size_t)n_views * (n_det / 2 + 1)))) return s;
+    if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RADON_ERR_DEVICE, "device synchronisation failed after plan setup");
+    }
+    return RADON_OK;
+}
+
+}  // namespace
+
+namespace rn {
+bool length_supported(int len) {
+    switch (len) {
+#define RN_CASE(L) case L:
+        RN_FOR_LENGTHS(RN_CASE)
+#undef RN_CASE
+        return true;
+        default:
+            return false;
+    }
+}
+
+hipError_t launch_fft_test(int len, int batch, int inverse, const float2* in, float2* out, const float2* tw,
+                           hipStream_t st) {
+    switch (len) {
+#define RN_CASE(L)                                                                                  \
+    case L: {                                                                                       \
+        constexpr int NT = fft_threads(L, 1);                                                       \
+        hipLaunchKernelGGL((k_fft_test<L, NT>), dim3(batch), dim3(NT), 0, st, in, out, tw, inverse); \
+        break;                                                                                      \
+    }
+        RN_FOR_LENGTHS(RN_CASE)
+#undef RN_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace rn
+
+extern "C" {
+
+radon_status_t radon_plan(radon_plan_t* out, int n, const double* angles, int n_views, int n_det,
+                          double sigma, int W) {
+    if (!out) return fail(RADON_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!angles) return fail(RADON_ERR_INVALID, "angles is NULL");
+    if (n < 8 || n % 2) return fail(RADON_ERR_INVALID, "n=%d must be even and >= 8", n);
+    if (n_det < 8 || n_det % 2) return fail(RADON_ERR_INVALID, "n_det=%d must be even and >= 8", n_det);
+    if (n_views < 1) return fail(RADON_ERR_INVALID, "n_views=%d must be >= 1", n_views);
+    if (!(sigma > 1.0) || fabs(sigma * n - round(sigma * n)) > 1e-9 || ((long)round(sigma * n)) % 2)
+        return fail(RADON_ERR_INVALID, "sigma*n must be an even integer with sigma > 1 (sigma=%g)", sigma);
+    if (W < 2 || W > 16 || W % 2) return fail(RADON_ERR_INVALID, "W=%d must be even, 2..16", W);
+    for (int a = 0; a < n_views; ++a)
+        if (!isfinite(angles[a])) return fail(RADON_ERR_INVALID, "angle %d is not finite", a);
+    if (fabs(sigma - 2.0) > 1e-12) return fail(RADON_ERR_UNSUPPORTED, "only sigma = 2 is implemented");
+    if (W != 4 && W != 6 && W != 8) return fail(RADON_ERR_UNSUPPORTED, "W=%d: only 4, 6, 8 are implemented", W);
+    if (n % 8) return fail(RADON_ERR_UNSUPPORTED, "n=%d must be a multiple of 8", n);
+    if (!is_supported_length(n)) return fail(RADON_ERR_UNSUPPORTED, "n=%d is not a supported FFT length", n);
+    if (!is_supported_length(n_det))
+        return fail(RADON_ERR_UNSUPPORTED, "n_det=%d is not a supported FFT length", n_det);
+    if ((int64_t)n_views * n_det + n_views >= (int64_t)1 << 30)
+        return fail(RADON_ERR_UNSUPPORTED, "too many samples");
+
+    radon_plan_s* plan = new (std::nothrow) radon_plan_s();
+    if (!plan) return fail(RADON_ERR_OOM, "host allocation failed");
+    if (hipGetDevice(&plan->p.device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete plan;
+        return fail(RADON_ERR_DEVICE, "no HIP device");
+    }
+    const radon_status_t s = build_plan(plan->p, n, angles, n_views, n_det, sigma, W);
+    if (s != RADON_OK) {
+        const std::string msg = g_last_error;
+        (void)hipDeviceSynchronize();
+        (void)hipGetLastError();
+        free_plan(plan->p);
+        delete plan;
+        g_last_error = msg;
+        return s;
+    }
+    *out = plan;
+    return ok();
+}
+
+radon_status_t radon_forward(radon_plan_t plan, const float* img_dev, float* sino_dev, void* stream) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    if (!img_dev || !sino_dev) return fail(RADON_ERR_INVALID, "NULL buffer");
+    if ((s = run_forward(plan->p, img_dev, sino_dev, (hipStream_t)stream))) return s;
+    return ok();
+}
+
+radon_status_t radon_adjoint(radon_plan_t plan, const float* sino_dev, float* img_dev, void* stream) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    if (!img_dev || !sino_dev) return fail(RADON_ERR_INVALID, "NULL buffer");
+    if ((s = run_adjoint(plan->p, sino_dev, img_dev, (hipStream_t)stream))) return s;
+    return ok();
+}
+
+radon_status_t radon_forward_batched(radon_plan_t plan, int batch, const float* imgs_dev, float* sinos_dev,
+                                     void* stream) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    if (batch < 0) return fail(RADON_ERR_INVALID, "batch=%d < 0", batch);
+    if (batch > 0 && (!imgs_dev || !sinos_dev)) return fail(RADON_ERR_INVALID, "NULL buffer");
+    const Plan& p = plan->p;
+    for (int b = 0; b < batch; ++b)
+        if ((s = run_forward(plan->p, imgs_dev + (size_t)b * p.n * p.n,
+                             sinos_dev + (size_t)b * p.n_views * p.n_det, (hipStream_t)stream)))
+            return s;
+    return ok();
+}
+
+radon_status_t radon_adjoint_batched(radon_plan_t plan, int batch, const float* sinos_dev, float* imgs_dev,
+                                     void* stream) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    if (batch < 0) return fail(RADON_ERR_INVALID, "batch=%d < 0", batch);
+    if (batch > 0 && (!imgs_dev || !sinos_dev)) return fail(RADON_ERR_INVALID, "NULL buffer");
+    const Plan& p = plan->p;
+    for (int b = 0; b < batch; ++b)
+        if ((s = run_adjoint(plan->p, sinos_dev + (size_t)b * p.n_views * p.n_det,
+                             imgs_dev + (size_t)b * p.n * p.n, (hipStream_t)stream)))
+            return s;
+    return ok();
+}
+
+radon_status_t radon_plan_sort_indices(radon_plan_t plan, int32_t* perm_host, int64_t perm_cap,
+                                       int32_t* offsets_host, int64_t offsets_cap) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    const Plan& p = plan->p;
+    if (perm_host && perm_cap < p.n_samples) return fail(RADON_ERR_INVALID, "perm_cap too small");
+    if (offsets_host && offsets_cap < p.n_bins + 1) return fail(RADON_ERR_INVALID, "offsets_cap too small");
+    hipError_t e = hipSuccess;
+    if (perm_host) e = hipMemcpy(perm_host, p.perm, sizeof(int) * p.n_samples, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && offsets_host)
+        e = hipMemcpy(offsets_host, p.offsets, sizeof(int) * (p.n_bins + 1), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(RADON_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+radon_status_t radon_plan_info(radon_plan_t plan, int64_t* info, int cap) {
+    if (!plan || !info) return fail(RADON_ERR_INVALID, "NULL argument");
+    const Plan& p = plan->p;
+    const int64_t v[] = {p.n, p.n_views, p.n_det, p.W, p.G, p.T, p.n_samples, p.n_bins,
+                         p.n_items, p.n_slots, (int64_t)p.bytes};
+    for (int k = 0; k < cap && k < (int)(sizeof(v) / sizeof(v[0])); ++k) info[k] = v[k];
+    return ok();
+}
+
+size_t radon_plan_device_bytes(radon_plan_t plan) { return plan ? plan->p.bytes : 0; }
+
+void radon_plan_destroy(radon_plan_t plan) {
+    if (!plan) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != plan->p.device) (void)hipSetDevice(plan->p.device);
+    (void)hipDeviceSynchronize();
+    free_plan(plan->p);
+    if (cur >= 0 && cur != plan->p.device) (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+    delete plan;
+}
+
+int radon_supported_length(int len) { return is_supported_length(len) ? 1 : 0; }
+
+const char* radon_status_string(radon_status_t status) {
+    switch (status) {
+        case RADON_OK: return "RADON_OK";
+        case RADON_ERR_INVALID: return "RADON_ERR_INVALID";
+        case RADON_ERR_UNSUPPORTED: return "RADON_ERR_UNSUPPORTED";
+        case RADON_ERR_OOM: return "RADON_ERR_OOM";
+        case RADON_ERR_DEVICE: return "RADON_ERR_DEVICE";
+        default: return "RADON_ERR_UNKNOWN";
+    }
+}
+
+const char* radon_last_error(void) { return g_last_error.c_str(); }
+
+radon_status_t radon_plan_set_profiling(radon_plan_t plan, int enable) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    Plan& p = plan->p;
+    p.profiling = enable != 0;
+    for (int k = 0; k < rn::ST_COUNT; ++k) { p.stage_ms[k] = 0; p.stage_cnt[k] = 0; }
+    for (auto& pt : p.pending) {
+        (void)hipEventSynchronize(pt.e1);
+        p.event_pool.push_back(pt.e0);
+        p.event_pool.push_back(pt.e1);
+    }
+    p.pending.clear();
+    return ok();
+}
+
+radon_status_t radon_plan_stage_times(radon_plan_t plan, double* ms, int64_t* counts, int cap) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    Plan& p = plan->p;
+    for (auto& pt : p.pending) {
+        if (hipEventSynchronize(pt.e1) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RADON_ERR_DEVICE, "event synchronisation failed");
+        }
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, pt.e0, pt.e1) == hipSuccess) {
+            p.stage_ms[pt.stage] += t;
+            p.stage_cnt[pt.stage] += 1;
+        }
+        p.event_pool.push_back(pt.e0);
+        p.event_pool.push_back(pt.e1);
+    }
+    p.pending.clear();
+    for (int k = 0; k < cap && k < rn::ST_COUNT; ++k) {
+        if (ms) ms[k] = p.stage_ms[k];
+        if (counts) counts[k] = p.stage_cnt[k];
+    }
+    return ok();
+}
+
+int radon_stage_count(void) { return rn::ST_COUNT; }
+
+const char* radon_stage_name(int stage) {
+    static const char* names[rn::ST_COUNT] = {"F1_row_fft", "F2_col_fft", "F34_interp_ray_ifft", "A1_ray_fft",
+                                              "A2_spread", "A2_reduce", "A3_col_ifft", "A4_row_ifft"};
+    return (stage >= 0 && stage < rn::ST_COUNT) ? names[stage] : "";
+}
+
+radon_status_t radon_debug_forward_grid(radon_plan_t plan, const float* img_dev, float* grid_dev, void* stream) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    if (!img_dev || !grid_dev) return fail(RADON_ERR_INVALID, "NULL buffer");
+    Plan& p = plan->p;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = launch_status(rn::launch_f1(p, img_dev, st), "F1"))) return s;
+    if ((s = launch_status(rn::launch_f2(p, st), "F2"))) return s;
+    if (hipMemcpyAsync(grid_dev, p.grid, sizeof(float2) * (size_t)(p.n + 1) * p.G, hipMemcpyDeviceToDevice, st) !=
+        hipSuccess)
+        return fail(RADON_ERR_DEVICE, "grid copy failed");
+    return ok();
+}
+
+radon_status_t radon_debug_adjoint_grid(radon_plan_t plan, const float* sino_dev, float* grid_dev, void* stream) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    if (!sino_dev || !grid_dev) return fail(RADON_ERR_INVALID, "NULL buffer");
+    Plan& p = plan->p;
+    hipStream_t st = (hipStream_t)stream;
+    const bool prof = p.profiling;
+    p.profiling = false;
+    s = run_adjoint_grid(p, sino_dev, st);
+    p.profiling = prof;
+    if (s) return s;
+    if (hipMemcpyAsync(grid_dev, p.grid, sizeof(float2) * (size_t)(p.n + 1) * p.G, hipMemcpyDeviceToDevice, st) !=
+        hipSuccess)
+        return fail(RADON_ERR_DEVICE, "grid copy failed");
+    return ok();
+}
+
+radon_status_t radon_fft_test(int len, int batch, int inverse, const float* in_dev, float* out_dev, void* stream) {
+    if (!in_dev || !out_dev) return fail(RADON_ERR_INVALID, "NULL buffer");
+    if (batch < 1) return fail(RADON_ERR_INVALID, "batch=%d < 1", batch);
+    if (!is_supported_length(len)) return fail(RADON_ERR_UNSUPPORTED, "len=%d not supported", len);
+    hipStream_t st = (hipStream_t)stream;
+    float2* tw = nullptr;
+    if (hipMalloc(&tw, sizeof(float2) * len) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RADON_ERR_OOM, "twiddle allocation failed");
+    }
+    const std::vector<float2> t = twiddles(len);
+    hipError_t e = hipMemcpy(tw, t.data(), sizeof(float2) * len, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = rn::launch_fft_test(len, batch, inverse, reinterpret_cast<const float2*>(in_dev),
+                                reinterpret_cast<float2*>(out_dev), tw, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(tw);
+    if (e != hipSuccess) return fail(RADON_ERR_DEVICE, "fft test failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+}  // extern "C"

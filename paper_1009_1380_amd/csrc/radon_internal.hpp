@@ -1,0 +1,85 @@
+// radon_internal.hpp - plan layout and kernel launchers shared by the
+// library's translation units (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "radon_kernels.hpp"
+
+// Supported FFT lengths (image size n and detector count n_det).
+#define RN_FOR_LENGTHS(X)                                                                        \
+    X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192)      \
+    X(256) X(320) X(384) X(512) X(640) X(768) X(1024) X(1280) X(1536) X(2048) X(2560) X(3072) \
+    X(4096)
+
+namespace rn {
+
+enum Stage {
+    ST_F1 = 0,
+    ST_F2,
+    ST_F34,
+    ST_A1,
+    ST_A2,
+    ST_A2R,
+    ST_A3,
+    ST_A4,
+    ST_COUNT
+};
+
+struct PendingTiming {
+    int stage;
+    hipEvent_t e0, e1;
+};
+
+struct Plan {
+    int device = 0;
+    int n = 0, n_views = 0, n_det = 0, W = 0, G = 0, T = 0, ntl = 0;
+    double sigma = 0, beta = 0;
+    int64_t n_samples = 0;   // real samples + mirrored Nyquist samples
+    int n_bins = 0, n_items = 0, n_slots = 0, n_splits = 0;
+    float kbL = 0;
+
+    // device tables
+    double2* cs = nullptr;       // per view (cos, sin), float64
+    float* psi_inv = nullptr;    // 1 / psi1[i], n
+    float2* shift_n = nullptr;   // e^{-i pi (i - n/2)/n}, n
+    float2* tw_n = nullptr;      // e^{-2 pi i t/n}, n
+    float2* tw_N = nullptr;      // e^{-2 pi i t/N}, N
+    float2* kbtab = nullptr;     // (phi, slope) per 1/L step on [0, W/2]
+    // device workspace
+    float2* T1 = nullptr;        // (n+1) x n complex64
+    float2* grid = nullptr;      // (n+1) x G complex64
+    float2* Yh = nullptr;        // n_views x (N/2+1) complex64
+    int* perm = nullptr;         // sorted sample ids
+    int* offsets = nullptr;      // n_bins + 1
+    WorkItem* items = nullptr;
+    SplitTile* splits = nullptr;
+    float2* partials = nullptr;
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+
+    bool profiling = false;
+    double stage_ms[ST_COUNT] = {};
+    int64_t stage_cnt[ST_COUNT] = {};
+    std::vector<PendingTiming> pending;
+    std::vector<hipEvent_t> event_pool;
+};
+
+// kernel launchers; each returns the launch status
+hipError_t launch_f1(const Plan& p, const float* img, hipStream_t st);
+hipError_t launch_f2(const Plan& p, hipStream_t st);
+hipError_t launch_f34(const Plan& p, float* sino, hipStream_t st);
+hipError_t launch_a1(const Plan& p, const float* sino, hipStream_t st);
+hipError_t launch_a2(const Plan& p, hipStream_t st);
+hipError_t launch_a2_reduce(const Plan& p, hipStream_t st);
+hipError_t launch_a3(const Plan& p, hipStream_t st);
+hipError_t launch_a4(const Plan& p, float* img, hipStream_t st);
+hipError_t launch_fft_test(int len, int batch, int inverse, const float2* in, float2* out,
+                           const float2* tw, hipStream_t st);
+
+bool length_supported(int len);
+
+}  // namespace rn

@@ -1,0 +1,263 @@
+"""Python binding of the gfx950 Radon NUFFT library (``libradon.so``).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels behind the C ABI declared in ``include/radon.h``. PyTorch supplies
+device memory and the current stream. If the library is not built the import
+of the binding still works, but every call raises ``RuntimeError``; there is
+no CPU fallback.
+
+    plan = Plan(n, angles, n_det, sigma=2.0, W=6)
+    sino = plan.forward(img)        # img: (n, n) float32 CUDA tensor
+    back = plan.adjoint(sino)       # exact transpose of forward
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libradon.so")
+HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "radon.h")
+
+RADON_OK, RADON_ERR_INVALID, RADON_ERR_UNSUPPORTED, RADON_ERR_OOM, RADON_ERR_DEVICE = range(5)
+
+_lib = None
+
+_c_int, _c_i64, _c_dbl, _vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+_SIGS = {
+    "radon_plan": (_c_int, [ctypes.POINTER(_vp), _c_int, ctypes.POINTER(_c_dbl), _c_int, _c_int, _c_dbl, _c_int]),
+    "radon_forward": (_c_int, [_vp, _vp, _vp, _vp]),
+    "radon_adjoint": (_c_int, [_vp, _vp, _vp, _vp]),
+    "radon_forward_batched": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
+    "radon_adjoint_batched": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
+    "radon_plan_sort_indices": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64]),
+    "radon_plan_info": (_c_int, [_vp, ctypes.POINTER(_c_i64), _c_int]),
+    "radon_plan_device_bytes": (ctypes.c_size_t, [_vp]),
+    "radon_plan_destroy": (None, [_vp]),
+    "radon_supported_length": (_c_int, [_c_int]),
+    "radon_status_string": (ctypes.c_char_p, [_c_int]),
+    "radon_last_error": (ctypes.c_char_p, []),
+    "radon_plan_set_profiling": (_c_int, [_vp, _c_int]),
+    "radon_plan_stage_times": (_c_int, [_vp, ctypes.POINTER(_c_dbl), ctypes.POINTER(_c_i64), _c_int]),
+    "radon_stage_count": (_c_int, []),
+    "radon_stage_name": (ctypes.c_char_p, [_c_int]),
+    "radon_debug_forward_grid": (_c_int, [_vp, _vp, _vp, _vp]),
+    "radon_debug_adjoint_grid": (_c_int, [_vp, _vp, _vp, _vp]),
+    "radon_fft_test": (_c_int, [_c_int, _c_int, _c_int, _vp, _vp, _vp]),
+}
+
+
+class RadonError(RuntimeError):
+    """A failing library call; ``status`` is the radon_status_t value."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+def lib():
+    """Load libradon.so (once). Raises RuntimeError if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1009_1380_amd.build.build()")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def declared_functions(header: str = HEADER_PATH):
+    """Names of the functions that include/radon.h declares."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(radon_[a-z_]+)\s*\(", text)))
+
+
+def _check(status: int, what: str):
+    if status != RADON_OK:
+        name = lib().radon_status_string(status).decode()
+        detail = lib().radon_last_error().decode()
+        msg = f"{what}: {name}: {detail}"
+        if status in (RADON_ERR_INVALID, RADON_ERR_UNSUPPORTED):
+            err = ValueError(msg)
+            err.status = status
+            raise err
+        raise RadonError(status, msg)
+
+
+def supported_length(length: int) -> bool:
+    return bool(lib().radon_supported_length(int(length)))
+
+
+def stage_names():
+    L = lib()
+    return [L.radon_stage_name(i).decode() for i in range(L.radon_stage_count())]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _dev_ptr(t, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor, got {t.device}")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Plan of the forward / adjoint Radon NUFFT for one geometry.
+
+    n: image side; angles: view angles in radians (float64, copied); n_det:
+    detector bins; sigma: oversampling (2); W: Kaiser-Bessel width (4, 6, 8).
+    The plan lives on the current CUDA device.
+    """
+
+    INFO_KEYS = ("n", "n_views", "n_det", "W", "G", "T", "n_samples", "n_bins",
+                 "n_items", "n_slots", "device_bytes")
+
+    def __init__(self, n: int, angles, n_det: int, sigma: float = 2.0, W: int = 6):
+        ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).ravel())
+        self.n, self.n_det, self.n_views = int(n), int(n_det), int(ang.size)
+        self.sigma, self.W = float(sigma), int(W)
+        self.angles = ang.copy()
+        h = ctypes.c_void_p()
+        st = lib().radon_plan(ctypes.byref(h), self.n, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              self.n_views, self.n_det, self.sigma, self.W)
+        _check(st, "radon_plan")
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().radon_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- transforms
+    def forward(self, img, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n_views, self.n_det), dtype=torch.float32, device=img.device)
+        _check(lib().radon_forward(self._h, _dev_ptr(img, (self.n, self.n), "img"),
+                                   _dev_ptr(out, (self.n_views, self.n_det), "out"), _stream_ptr(stream)),
+               "radon_forward")
+        return out
+
+    def adjoint(self, sino, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n, self.n), dtype=torch.float32, device=sino.device)
+        _check(lib().radon_adjoint(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
+                                   _dev_ptr(out, (self.n, self.n), "out"), _stream_ptr(stream)),
+               "radon_adjoint")
+        return out
+
+    def forward_batched(self, imgs, out=None, stream=None):
+        torch = _torch()
+        b = int(imgs.shape[0])
+        if out is None:
+            out = torch.empty((b, self.n_views, self.n_det), dtype=torch.float32, device=imgs.device)
+        _check(lib().radon_forward_batched(self._h, b, _dev_ptr(imgs, (b, self.n, self.n), "imgs"),
+                                           _dev_ptr(out, (b, self.n_views, self.n_det), "out"),
+                                           _stream_ptr(stream)), "radon_forward_batched")
+        return out
+
+    def adjoint_batched(self, sinos, out=None, stream=None):
+        torch = _torch()
+        b = int(sinos.shape[0])
+        if out is None:
+            out = torch.empty((b, self.n, self.n), dtype=torch.float32, device=sinos.device)
+        _check(lib().radon_adjoint_batched(self._h, b, _dev_ptr(sinos, (b, self.n_views, self.n_det), "sinos"),
+                                           _dev_ptr(out, (b, self.n, self.n), "out"), _stream_ptr(stream)),
+               "radon_adjoint_batched")
+        return out
+
+    # -- introspection and test hooks
+    def info(self) -> dict:
+        arr = (ctypes.c_int64 * len(self.INFO_KEYS))()
+        _check(lib().radon_plan_info(self._h, arr, len(self.INFO_KEYS)), "radon_plan_info")
+        return dict(zip(self.INFO_KEYS, [int(v) for v in arr]))
+
+    def sort_indices(self):
+        inf = self.info()
+        perm = np.empty(inf["n_samples"], dtype=np.int32)
+        offs = np.empty(inf["n_bins"] + 1, dtype=np.int32)
+        _check(lib().radon_plan_sort_indices(self._h, perm.ctypes.data_as(ctypes.c_void_p), perm.size,
+                                             offs.ctypes.data_as(ctypes.c_void_p), offs.size),
+               "radon_plan_sort_indices")
+        return perm, offs
+
+    def set_profiling(self, enable: bool = True):
+        _check(lib().radon_plan_set_profiling(self._h, int(bool(enable))), "radon_plan_set_profiling")
+
+    def stage_times(self) -> dict:
+        k = lib().radon_stage_count()
+        ms = (ctypes.c_double * k)()
+        cnt = (ctypes.c_int64 * k)()
+        _check(lib().radon_plan_stage_times(self._h, ms, cnt, k), "radon_plan_stage_times")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(stage_names())}
+
+    def debug_forward_grid(self, img, stream=None):
+        torch = _torch()
+        G = 2 * self.n
+        out = torch.empty((self.n + 1, G, 2), dtype=torch.float32, device=img.device)
+        _check(lib().radon_debug_forward_grid(self._h, _dev_ptr(img, (self.n, self.n), "img"),
+                                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+               "radon_debug_forward_grid")
+        return torch.view_as_complex(out)
+
+    def debug_adjoint_grid(self, sino, stream=None):
+        torch = _torch()
+        G = 2 * self.n
+        out = torch.empty((self.n + 1, G, 2), dtype=torch.float32, device=sino.device)
+        _check(lib().radon_debug_adjoint_grid(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
+                                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+               "radon_debug_adjoint_grid")
+        return torch.view_as_complex(out)
+
+
+def fft_test(x, inverse: bool = False, stream=None):
+    """Batched LDS FFT of the rows of a complex64 CUDA tensor (batch, len)."""
+    torch = _torch()
+    if x.dtype != torch.complex64 or x.dim() != 2 or not x.is_contiguous() or x.device.type != "cuda":
+        raise ValueError("x must be a contiguous (batch, len) complex64 device tensor")
+    out = torch.empty_like(x)
+    _check(lib().radon_fft_test(int(x.shape[1]), int(x.shape[0]), int(bool(inverse)),
+                                ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                _stream_ptr(stream)), "radon_fft_test")
+    return out

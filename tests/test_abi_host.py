@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/radon.h declares, and rejects bad arguments before
+touching a device."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from paper_1009_1380_amd import radon as rb
+
+pytestmark = pytest.mark.skipif(not os.path.exists(rb.LIB_PATH), reason="libradon.so not built")
+
+
+def test_library_exports_every_declared_function():
+    L = rb.lib()
+    names = rb.declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(rb._SIGS), "binding signatures and header disagree"
+
+
+def test_status_strings():
+    L = rb.lib()
+    assert L.radon_status_string(0) == b"RADON_OK"
+    assert L.radon_status_string(2) == b"RADON_ERR_UNSUPPORTED"
+    assert L.radon_status_string(99) == b"RADON_ERR_UNKNOWN"
+
+
+def test_supported_lengths():
+    for L in [8, 16, 24, 40, 128, 1536, 2560, 4096]:
+        assert rb.supported_length(L)
+    for L in [0, 7, 14, 2562, 7 * 128, 8192 * 2]:
+        assert not rb.supported_length(L)
+
+
+def test_stage_names():
+    names = rb.stage_names()
+    assert names[0] == "F1_row_fft" and "A2_spread" in names and len(names) == 8
+
+
+def _plan_status(n, nv, n_det, sigma, W, angles="ok"):
+    L = rb.lib()
+    h = ctypes.c_void_p(123)
+    if angles == "null":
+        ptr = None
+    else:
+        a = np.linspace(0, 3, max(nv, 1))
+        if angles == "nan":
+            a[0] = np.nan
+        ptr = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st = L.radon_plan(ctypes.byref(h), n, ptr, nv, n_det, sigma, W)
+    return st, h.value
+
+
+@pytest.mark.parametrize("args,status", [
+    ((7, 4, 16, 2.0, 6), rb.RADON_ERR_INVALID),      # odd n
+    ((4, 4, 16, 2.0, 6), rb.RADON_ERR_INVALID),      # n < 8
+    ((16, 4, 15, 2.0, 6), rb.RADON_ERR_INVALID),     # odd n_det
+    ((16, 0, 16, 2.0, 6), rb.RADON_ERR_INVALID),     # no views
+    ((16, 4, 16, 2.0, 5), rb.RADON_ERR_INVALID),     # odd W
+    ((16, 4, 16, 2.0, 18), rb.RADON_ERR_INVALID),    # W too large
+    ((16, 4, 16, 1.0, 6), rb.RADON_ERR_INVALID),     # sigma <= 1
+    ((16, 4, 16, 1.5, 6), rb.RADON_ERR_UNSUPPORTED),  # valid sigma, not implemented
+    ((16, 4, 16, 2.0, 10), rb.RADON_ERR_UNSUPPORTED),  # valid W, not implemented
+    ((20, 4, 16, 2.0, 6), rb.RADON_ERR_UNSUPPORTED),  # n not a multiple of 8
+    ((16, 4, 14, 2.0, 6), rb.RADON_ERR_UNSUPPORTED),  # n_det not a supported length
+])
+def test_plan_argument_errors(args, status):
+    st, h = _plan_status(*args)
+    assert st == status
+    assert h is None or h == 0
+    assert rb.lib().radon_last_error() != b""
+
+
+def test_plan_null_and_nan_angles():
+    assert _plan_status(16, 4, 16, 2.0, 6, angles="null")[0] == rb.RADON_ERR_INVALID
+    assert _plan_status(16, 4, 16, 2.0, 6, angles="nan")[0] == rb.RADON_ERR_INVALID
+    L = rb.lib()
+    a = np.zeros(4)
+    assert L.radon_plan(None, 16, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 4, 16, 2.0, 6) \
+        == rb.RADON_ERR_INVALID
+
+
+def test_null_plan_calls():
+    L = rb.lib()
+    assert L.radon_forward(None, None, None, None) == rb.RADON_ERR_INVALID
+    assert L.radon_adjoint(None, None, None, None) == rb.RADON_ERR_INVALID
+    assert L.radon_plan_device_bytes(None) == 0
+    L.radon_plan_destroy(None)   # NULL-safe
+    assert L.radon_fft_test(2562, 1, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == rb.RADON_ERR_UNSUPPORTED
+    assert L.radon_fft_test(64, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == rb.RADON_ERR_INVALID
