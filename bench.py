@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X Radon NUFFT: forward + adjoint pairs per second.
+
+One step is one forward Radon transform and one adjoint of its result on the
+full-size slice: a 2560 x 2560 float32 disk phantom (200 disks, radii 10-300
+px, plus N(0, 1e-2^2) noise), 1024 views uniform in [0, pi), 2560 detector
+bins, oversampling 2, Kaiser-Bessel width 6. The value is sinogram samples
+through one forward+adjoint pair per second (Gsamples/s), inputs resident in
+HBM. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 30] [--warmup 5]
+
+Only one GPU is used; --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Radon NUFFT fwd+adj Gsamples/s; solve time to fixed residual, warm vs cold"
+N_IMG, N_VIEWS, N_DET, SIGMA, W = 2560, 1024, 2560, 2.0, 6
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_full_slice_2560.json")
+
+
+def kernel_bytes(n: int, n_views: int, n_det: int):
+    """Algorithmic HBM bytes per launch of each kernel (each array touched once).
+
+    The grid is the Hermitian half plane, (n+1) x 2n complex64; T1 is the
+    row-transform intermediate, (n+1) x n complex64.
+    """
+    G = 2 * n
+    img = 4 * n * n
+    t1 = 8 * (n + 1) * n
+    grid = 8 * (n + 1) * G
+    sino = 4 * n_views * n_det
+    yh = 8 * n_views * (n_det // 2 + 1)
+    xr = yh
+    return {
+        "F1_row_fft": img + t1,
+        "F2_col_fft": t1 + grid,
+        "F3_interp": grid + xr,
+        "F4_ray_ifft": xr + sino,
+        "A1_ray_fft": sino + yh,
+        "A2_spread": yh + grid,
+        "A2_reduce": 0,
+        "A3_col_ifft": grid + t1,
+        "A4_row_ifft": t1 + img,
+    }
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1009_1380_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, n_launch_bytes: int):
+    """HBM bytes per launch from committed counter runs, if they are current."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n_views_sample: int):
+    """Time the FP64 oracle (forward + adjoint) on a bounded sample: the same
+    image and detector, every (1024/n_views_sample)-th view."""
+    import numpy as np
+
+    from oracle.grid import _WORKERS, grid_adjoint, grid_forward
+    from radon_inputs import config2_phantom, uniform_angles
+
+    x = config2_phantom(0, N_IMG).astype(np.float64)
+    ang = uniform_angles(N_VIEWS)[:: N_VIEWS // n_views_sample]
+    t0 = time.perf_counter()
+    y = grid_forward(x, ang, N_DET, SIGMA, W)
+    t1 = time.perf_counter()
+    grid_adjoint(y, ang, N_IMG, SIGMA, W)
+    t2 = time.perf_counter()
+    samples = len(ang) * N_DET
+    return {
+        "value": samples / (t2 - t0) / 1e9,
+        "unit": "Gsamples/s",
+        "cores": int(_WORKERS),
+        "kind": "oracle",
+        "sample": (f"FP64 O-grid forward+adjoint of the 2560^2 disk phantom on {len(ang)} of the "
+                   f"1024 views x 2560 bins ({samples} samples): fwd {t1 - t0:.2f} s, "
+                   f"adj {t2 - t1:.2f} s; scipy.fft workers and BLAS threads as listed"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-views", type=int, default=1024, help="views in the CPU-oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(slices shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: launched with WORLD_SIZE > 1; only one GPU is used", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1009_1380_amd import Plan
+    from radon_inputs import config2_phantom, uniform_angles
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("bench: building inputs and plan", file=sys.stderr, flush=True)
+    x = torch.from_numpy(config2_phantom(0, N_IMG)).to(dev)
+    ang = uniform_angles(N_VIEWS)
+    t_plan0 = time.perf_counter()
+    plan = Plan(N_IMG, ang, N_DET, SIGMA, W)
+    t_plan = time.perf_counter() - t_plan0
+    sino = torch.empty((N_VIEWS, N_DET), dtype=torch.float32, device=dev)
+    back = torch.empty((N_IMG, N_IMG), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.forward(x, out=sino, stream=stream)
+        plan.adjoint(sino, out=back, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K steps between events on the stream the kernels run on
+    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+
+    # forward and adjoint separately
+    def time_loop(fn, k):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(k):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    t_fwd = time_loop(lambda: plan.forward(x, out=sino, stream=stream), args.steps)
+    t_adj = time_loop(lambda: plan.adjoint(sino, out=back, stream=stream), args.steps)
+
+    # per-kernel durations: same steps with each launch bracketed by events
+    plan.set_profiling(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    st = plan.stage_times()
+    plan.set_profiling(False)
+    kbytes = kernel_bytes(N_IMG, N_VIEWS, N_DET)
+    stages = {}
+    for name, (ms, cnt) in st.items():
+        if cnt:
+            avg_us = 1e3 * ms / cnt
+            gbs = kbytes[name] / (avg_us * 1e-6) / 1e9 if kbytes[name] else None
+            stages[name] = {"avg_us": round(avg_us, 2), "launches": cnt,
+                            "alg_bytes": kbytes[name], "alg_GBps": round(gbs, 1) if gbs else None}
+    dominant = max(stages, key=lambda k: stages[k]["avg_us"] * stages[k]["launches"])
+    d = stages[dominant]
+    achieved = d["alg_bytes"] / (d["avg_us"] * 1e-6) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": dominant,
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": load_traffic(dominant, d["alg_bytes"]),
+    }
+    samples = N_VIEWS * N_DET
+    value = samples / (ms_step * 1e-3) / 1e9
+    pair_bytes = sum(kbytes[k] for k in kbytes)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "full-size slice: 2560^2 disk phantom (200 disks, radii 10-300, +N(0,1e-2^2)), "
+                        "1024 views in [0,pi) x 2560 bins, sigma=2, KB W=6; one step = forward + adjoint",
+            "n": N_IMG, "n_views": N_VIEWS, "n_det": N_DET, "sigma": SIGMA, "W": W,
+            "parallelism": "single GPU",
+        },
+        "t_fwd_ms": round(t_fwd, 4),
+        "t_adj_ms": round(t_adj, 4),
+        "wall_s_timed": round(wall, 4),
+        "plan_s": round(t_plan, 3),
+        "pair_alg_bytes": pair_bytes,
+        "pair_alg_GBps": round(pair_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "stages": stages,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_views)
+    else:
+        line["cpu_baseline"] = None
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

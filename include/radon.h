@@ -95,11 +95,14 @@ radon_status_t radon_adjoint_batched(radon_plan_t plan, int batch, const float* 
  * Test hook: copy the plan's stable sample sort to host memory. The sorted
  * samples are the n_views*n_det polar samples j = a*n_det + q + n_det/2
  * followed by n_views mirrored Nyquist samples (view a at q = +n_det/2).
- * Keys are the footprint-origin tile (section "fast radon transform",
- * paragraph 4, read as uniform tiles): o = (floor(u) - W/2 + 1 + G/2) mod G,
- * key = (o_v div T)*(G/T) + (o_u div T). perm gets the sorted sample ids
- * (perm_cap >= n_samples), offsets the n_bins+1 bin starts. Either pointer
- * may be NULL. Sizes come from radon_plan_info.
+ * Bins are uniform T x T tiles of the oversampled grid (section "fast radon
+ * transform", paragraph 4, read as uniform tiles) keyed by the tile of the
+ * footprint origin o = (floor(u) - W/2 + 1 + G/2) mod G,
+ * key = (o_v div T)*(G/T) + (o_u div T), refined by the footprint's edge
+ * class c (0 inside, 1 crosses the u edge, 2 both, 3 the v edge): the sort is
+ * stable by 4*key + c. perm gets the sorted sample ids (perm_cap >=
+ * n_samples), offsets the 4*n_bins+1 class starts. Either pointer may be
+ * NULL. Sizes come from radon_plan_info.
  */
 radon_status_t radon_plan_sort_indices(radon_plan_t plan, int32_t* perm_host, int64_t perm_cap,
                                        int32_t* offsets_host, int64_t offsets_cap);
@@ -107,7 +110,8 @@ radon_status_t radon_plan_sort_indices(radon_plan_t plan, int32_t* perm_host, in
 /*
  * Plan facts for tests and benchmarks. info[k] (k < cap) receives:
  *  0 n, 1 n_views, 2 n_det, 3 W, 4 G, 5 tile T, 6 sorted samples,
- *  7 bins, 8 spreading work items, 9 partial slots, 10 device bytes.
+ *  7 bins (tiles), 8 spreading work items, 9 partial slots, 10 device bytes,
+ *  11 forward interpolation work items.
  */
 radon_status_t radon_plan_info(radon_plan_t plan, int64_t* info, int cap);
 

@@ -15,12 +15,19 @@ and a stable sort of the samples by key (ties keep increasing sample index).
 With W <= T a footprint whose origin is in tile (tx, ty) lies inside tiles
 tx..tx+1 by ty..ty+1, so the samples touching an output tile are those of its
 own bin and of its left, upper and upper-left neighbours.
+
+Within a bin the samples are further grouped by which tile edges their
+footprint crosses (edge class: 0 inside the tile, 1 crosses only the edge of
+increasing o_u, 2 crosses both, 3 crosses only the edge of increasing o_v), so
+that each neighbouring tile reads one contiguous run of the samples that
+actually reach it: the u-neighbour classes 1-2, the v-neighbour classes 2-3,
+the diagonal neighbour class 2. The refined key is 4 * key + class.
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["sample_keys", "stable_sort", "bin_offsets"]
+__all__ = ["sample_keys", "edge_class", "refined_keys", "stable_sort", "bin_offsets"]
 
 
 def sample_keys(u, v, G: int, W: int, T: int) -> np.ndarray:
@@ -30,6 +37,21 @@ def sample_keys(u, v, G: int, W: int, T: int) -> np.ndarray:
     ou = (np.floor(u).astype(np.int64) - W // 2 + 1 + G // 2) % G
     ov = (np.floor(v).astype(np.int64) - W // 2 + 1 + G // 2) % G
     return (ov // T) * (G // T) + (ou // T)
+
+
+def edge_class(u, v, G: int, W: int, T: int) -> np.ndarray:
+    """0: footprint inside its tile; 1: crosses the o_u edge only; 2: both;
+    3: the o_v edge only."""
+    ou = (np.floor(u).astype(np.int64) - W // 2 + 1 + G // 2) % G
+    ov = (np.floor(v).astype(np.int64) - W // 2 + 1 + G // 2) % G
+    cu = (ou % T) + W - 1 >= T
+    cv = (ov % T) + W - 1 >= T
+    return np.where(cu & cv, 2, np.where(cu, 1, np.where(cv, 3, 0))).astype(np.int64)
+
+
+def refined_keys(u, v, G: int, W: int, T: int) -> np.ndarray:
+    """4 * tile key + edge class."""
+    return 4 * sample_keys(u, v, G, W, T) + edge_class(u, v, G, W, T)
 
 
 def stable_sort(keys) -> np.ndarray:

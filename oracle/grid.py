@@ -41,7 +41,9 @@ from .kb import deapod_factors, kb_beta, kb_phi
 __all__ = ["GridParams", "grid_forward", "grid_adjoint", "grid_fft2", "grid_interp",
            "grid_spread", "ray_spectrum", "ray_synthesis"]
 
-_WORKERS = max(1, os.cpu_count() or 1)
+# FFT worker threads: the CPUs this process may use, at most 16 (the host
+# share of one GPU on the machines this runs on).
+_WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 class GridParams:

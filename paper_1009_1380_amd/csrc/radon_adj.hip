@@ -26,8 +26,8 @@ hipError_t launch_a1(const Plan& p, const float* sino, hipStream_t st) {
 template <int W, int T>
 static hipError_t launch_a2_wt(const Plan& p, hipStream_t st) {
     if (p.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_a2_spread<W, T>), dim3(p.n_items), dim3(64), 0, st, p.items, p.offsets,
-                       p.perm, p.Yh, p.cs, p.kbtab, p.kbL, p.grid, p.partials, p.G, p.n_det,
+    hipLaunchKernelGGL((k_a2_spread<W, T>), dim3(p.n_items), dim3(64), 0, st, p.items, p.offs4,
+                       p.perm, p.Yh, p.cs, p.kbc, p.kbS, p.grid, p.partials, p.G, p.n_det,
                        p.n_views);
     return hipGetLastError();
 }

@@ -42,9 +42,11 @@ radon_status_t ok() {
 
 // Visits per spreading work item; longer tile lists are split and their
 // partial tiles summed in a fixed order.
-constexpr int kA2Chunk = 512;
-// Kaiser-Bessel table entries per unit of t.
-constexpr int kKbL = 1024;
+constexpr int kA2Chunk = 1024;
+// Samples per forward interpolation work item.
+constexpr int kF3Chunk = 2048;
+// Cubic Kaiser-Bessel pieces per unit of t (a power of two).
+constexpr int kKbS = 32;
 
 // I0(x) by its power series sum ((x/2)^(2k) / (k!)^2); x <= 40 here.
 double bessel_i0(double x) {
@@ -73,6 +75,30 @@ double kb_phihat(double f, int W, double beta) {
     else if (z2 < 0) { const double z = sqrt(-z2); r = sin(z) / z; }
     else r = 1.0;
     return r * W / bessel_i0(beta);
+}
+
+// Cubic c0 + c1 f + c2 f^2 + c3 f^3 through phi at the four Chebyshev points
+// of piece i (t = (i + f)/S, f in [0, 1)), solved in float64.
+void kb_cubic_piece(int i, int S, int W, double beta, double c[4]) {
+    double A[4][5];
+    for (int k = 0; k < 4; ++k) {
+        const double f = 0.5 + 0.5 * cos(M_PI * (k + 0.5) / 4.0);
+        double pw = 1.0;
+        for (int j = 0; j < 4; ++j) { A[k][j] = pw; pw *= f; }
+        A[k][4] = kb_phi((i + f) / S, W, beta);
+    }
+    for (int col = 0; col < 4; ++col) {   // Gaussian elimination, partial pivoting
+        int piv = col;
+        for (int r = col + 1; r < 4; ++r)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        for (int j = 0; j < 5; ++j) std::swap(A[col][j], A[piv][j]);
+        for (int r = 0; r < 4; ++r) {
+            if (r == col) continue;
+            const double m = A[r][col] / A[col][col];
+            for (int j = col; j < 5; ++j) A[r][j] -= m * A[col][j];
+        }
+    }
+    for (int j = 0; j < 4; ++j) c[j] = A[j][4] / A[j][j];
 }
 
 bool is_supported_length(int len) { return rn::length_supported(len); }
@@ -166,7 +192,8 @@ radon_status_t run_forward(Plan& p, const float* img, float* sino, hipStream_t s
     radon_status_t s;
     if ((s = launch_status(staged(p, rn::ST_F1, st, [&] { return rn::launch_f1(p, img, st); }), "F1"))) return s;
     if ((s = launch_status(staged(p, rn::ST_F2, st, [&] { return rn::launch_f2(p, st); }), "F2"))) return s;
-    if ((s = launch_status(staged(p, rn::ST_F34, st, [&] { return rn::launch_f34(p, sino, st); }), "F34"))) return s;
+    if ((s = launch_status(staged(p, rn::ST_F3, st, [&] { return rn::launch_f3(p, st); }), "F3"))) return s;
+    if ((s = launch_status(staged(p, rn::ST_F4, st, [&] { return rn::launch_f4(p, sino, st); }), "F4"))) return s;
     return RADON_OK;
 }
 
@@ -205,8 +232,9 @@ radon_status_t sort_samples(Plan& p, std::vector<int>& offsets_host) {
     }
     hipLaunchKernelGGL(rn::k_sample_keys, dim3((total + 255) / 256), dim3(256), 0, 0, p.cs, k0, v0,
                        p.n_views, p.n_det, p.G, p.W, p.T);
+    const int n_keys = 4 * p.n_bins;
     int bits = 0;
-    while ((1 << bits) < p.n_bins) ++bits;
+    while ((1 << bits) < n_keys) ++bits;
     for (int shift = 0; shift < bits; shift += 4) {
         hipLaunchKernelGGL(rn::k_sort_hist, dim3(nblocks), dim3(rn::SORT_NT), 0, 0, k0, total, shift, hist, nblocks);
         hipLaunchKernelGGL(rn::k_exclusive_scan, dim3(1), dim3(1024), 0, 0, hist, rn::SORT_RADIX * nblocks);
@@ -215,36 +243,45 @@ radon_status_t sort_samples(Plan& p, std::vector<int>& offsets_host) {
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
-    hipLaunchKernelGGL(rn::k_bin_offsets, dim3((p.n_bins + 1 + 255) / 256), dim3(256), 0, 0, k0, total,
-                       p.offsets, p.n_bins);
+    hipLaunchKernelGGL(rn::k_bin_offsets, dim3((n_keys + 1 + 255) / 256), dim3(256), 0, 0, k0, total,
+                       p.offs4, n_keys);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpy(p.perm, v0, sizeof(int) * total, hipMemcpyDeviceToDevice);
-    offsets_host.assign(p.n_bins + 1, 0);
+    offsets_host.assign(n_keys + 1, 0);
     if (e == hipSuccess)
-        e = hipMemcpy(offsets_host.data(), p.offsets, sizeof(int) * (p.n_bins + 1), hipMemcpyDeviceToHost);
+        e = hipMemcpy(offsets_host.data(), p.offs4, sizeof(int) * (n_keys + 1), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     cleanup();
     if (e != hipSuccess) return fail(RADON_ERR_DEVICE, "sample sort failed: %s", hipGetErrorString(e));
     return RADON_OK;
 }
 
-// Spreading work list: one item per visit chunk of each half-plane output
-// tile (tile column 0 holds the mx = G/2 line, columns ntl/2..ntl-1 hold
-// mx = 0..G/2-1).
-radon_status_t build_work(Plan& p, const std::vector<int>& offs) {
+// Work lists. Spreading: one item per chunk of the visit list of each output
+// tile of the half plane (tile column 0 holds the mx = G/2 line, columns
+// ntl/2..ntl-1 hold mx = 0..G/2-1); the visit list is the diagonal
+// neighbour's class 2, the v-neighbour's classes 2-3, the u-neighbour's
+// classes 1-2 and all of the own bin. Forward: one item per chunk of the own
+// bin of every forward tile (columns 0 and ntl/2-1..ntl-1).
+radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
     const int ntl = p.ntl;
-    auto count = [&](int b) { return offs[b + 1] - offs[b]; };
-    std::vector<int> cols;
-    cols.push_back(0);
-    for (int cx = ntl / 2; cx < ntl; ++cx) cols.push_back(cx);
-    std::vector<rn::WorkItem> items;
+    auto run = [&](int bin, int c0, int c1) { return o4[4 * bin + c1] - o4[4 * bin + c0]; };
+    std::vector<rn::TileItem> items, fitems;
     std::vector<rn::SplitTile> splits;
     int slots = 0;
     for (int cy = 0; cy < ntl; ++cy) {
-        for (int cx : cols) {
+        for (int cx = 0; cx < ntl; ++cx) {
+            const bool half = (cx == 0) || (cx >= ntl / 2);
+            const bool fwd = (cx == 0) || (cx >= ntl / 2 - 1);
+            const int own = cy * ntl + cx;
+            if (fwd) {
+                const int n_own = run(own, 0, 4);
+                for (int k = 0; k < n_own; k += kF3Chunk)
+                    fitems.push_back({cx, cy, o4[4 * own] + k, std::min(kF3Chunk, n_own - k), -1, 0, 0, 0});
+            }
+            if (!half) continue;
             const int xl = (cx + ntl - 1) % ntl, yu = (cy + ntl - 1) % ntl;
-            const int total = count(yu * ntl + xl) + count(yu * ntl + cx) + count(cy * ntl + xl) +
-                              count(cy * ntl + cx);
+            const int total = run(yu * ntl + xl, 2, 3) + run(yu * ntl + cx, 2, 4) + run(cy * ntl + xl, 1, 3) +
+                              run(own, 0, 4);
             if (total <= kA2Chunk) {
                 items.push_back({cx, cy, 0, total, -1, 0, 0, 0});
             } else {
@@ -257,15 +294,19 @@ radon_status_t build_work(Plan& p, const std::vector<int>& offs) {
             }
         }
     }
-    // longest items first so the tail of the launch is short
-    std::stable_sort(items.begin(), items.end(),
-                     [](const rn::WorkItem& a, const rn::WorkItem& b) { return a.count > b.count; });
+    // longest items first so the tail of each launch is short
+    auto longer = [](const rn::TileItem& a, const rn::TileItem& b) { return a.count > b.count; };
+    std::stable_sort(items.begin(), items.end(), longer);
+    std::stable_sort(fitems.begin(), fitems.end(), longer);
     p.n_items = (int)items.size();
+    p.n_fitems = (int)fitems.size();
     p.n_splits = (int)splits.size();
     p.n_slots = slots;
     radon_status_t s;
     if ((s = dev_alloc(p, &p.items, items.size()))) return s;
-    if ((s = upload(p.items, items))) return s;
+    if (!items.empty() && (s = upload(p.items, items))) return s;
+    if ((s = dev_alloc(p, &p.fitems, fitems.size()))) return s;
+    if (!fitems.empty() && (s = upload(p.fitems, fitems))) return s;
     if ((s = dev_alloc(p, &p.splits, splits.size()))) return s;
     if (!splits.empty() && (s = upload(p.splits, splits))) return s;
     if ((s = dev_alloc(p, &p.partials, (size_t)std::max(slots, 1) * p.T * p.T))) return s;
@@ -290,7 +331,7 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
     p.n_bins = p.ntl * p.ntl;
     p.n_samples = (int64_t)n_views * n_det + n_views;
     p.beta = M_PI * sqrt((W / sigma) * (W / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
-    p.kbL = (float)kKbL;
+    p.kbS = (float)kKbS;
 
     // host tables in float64, rounded once
     std::vector<double2> cs(n_views);
@@ -302,13 +343,13 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
         const double a = -M_PI * ((double)i - n / 2) / (double)n;
         shift[i] = make_float2((float)cos(a), (float)sin(a));
     }
-    const int ntab = (W / 2) * kKbL;
-    std::vector<double> phi(ntab + 1);
-    for (int i = 0; i < ntab; ++i) phi[i] = kb_phi((double)i / kKbL, W, p.beta);
-    phi[ntab] = 1.0 / bessel_i0(p.beta);   // limit from inside the support
-    std::vector<float2> kb(ntab + 1);
-    for (int i = 0; i < ntab; ++i) kb[i] = make_float2((float)phi[i], (float)(phi[i + 1] - phi[i]));
-    kb[ntab] = make_float2((float)phi[ntab], 0.f);
+    const int npiece = (W / 2) * kKbS;
+    std::vector<float4> kbc(npiece);
+    for (int i = 0; i < npiece; ++i) {
+        double c[4];
+        kb_cubic_piece(i, kKbS, W, p.beta, c);
+        kbc[i] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
+    }
 
     radon_status_t s;
     if ((s = dev_alloc(p, &p.cs, n_views)) || (s = upload(p.cs, cs))) return s;
@@ -316,15 +357,16 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
     if ((s = dev_alloc(p, &p.shift_n, n)) || (s = upload(p.shift_n, shift))) return s;
     if ((s = dev_alloc(p, &p.tw_n, n)) || (s = upload(p.tw_n, twiddles(n)))) return s;
     if ((s = dev_alloc(p, &p.tw_N, n_det)) || (s = upload(p.tw_N, twiddles(n_det)))) return s;
-    if ((s = dev_alloc(p, &p.kbtab, kb.size())) || (s = upload(p.kbtab, kb))) return s;
+    if ((s = dev_alloc(p, &p.kbc, kbc.size())) || (s = upload(p.kbc, kbc))) return s;
     if ((s = dev_alloc(p, &p.perm, (size_t)p.n_samples))) return s;
-    if ((s = dev_alloc(p, &p.offsets, (size_t)p.n_bins + 1))) return s;
+    if ((s = dev_alloc(p, &p.offs4, (size_t)4 * p.n_bins + 1))) return s;
     std::vector<int> offs;
     if ((s = sort_samples(p, offs))) return s;
     if ((s = build_work(p, offs))) return s;
     if ((s = dev_alloc(p, &p.T1, (size_t)(n + 1) * n))) return s;
     if ((s = dev_alloc(p, &p.grid, (size_t)(n + 1) * G))) return s;
     if ((s = dev_alloc(p, &p.Yh, (size_t)n_views * (n_det / 2 + 1)))) return s;
+    if ((s = dev_alloc(p, &p.Xr, (size_t)n_views * (n_det / 2 + 1)))) return s;
     if (hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         return fail(RADON_ERR_DEVICE, "device synchronisation failed after plan setup");
@@ -459,11 +501,12 @@ radon_status_t radon_plan_sort_indices(radon_plan_t plan, int32_t* perm_host, in
     if ((s = check_plan(plan))) return s;
     const Plan& p = plan->p;
     if (perm_host && perm_cap < p.n_samples) return fail(RADON_ERR_INVALID, "perm_cap too small");
-    if (offsets_host && offsets_cap < p.n_bins + 1) return fail(RADON_ERR_INVALID, "offsets_cap too small");
+    if (offsets_host && offsets_cap < 4 * (int64_t)p.n_bins + 1)
+        return fail(RADON_ERR_INVALID, "offsets_cap too small");
     hipError_t e = hipSuccess;
     if (perm_host) e = hipMemcpy(perm_host, p.perm, sizeof(int) * p.n_samples, hipMemcpyDeviceToHost);
     if (e == hipSuccess && offsets_host)
-        e = hipMemcpy(offsets_host, p.offsets, sizeof(int) * (p.n_bins + 1), hipMemcpyDeviceToHost);
+        e = hipMemcpy(offsets_host, p.offs4, sizeof(int) * (4 * (size_t)p.n_bins + 1), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(RADON_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
     return ok();
 }
@@ -472,7 +515,7 @@ radon_status_t radon_plan_info(radon_plan_t plan, int64_t* info, int cap) {
     if (!plan || !info) return fail(RADON_ERR_INVALID, "NULL argument");
     const Plan& p = plan->p;
     const int64_t v[] = {p.n, p.n_views, p.n_det, p.W, p.G, p.T, p.n_samples, p.n_bins,
-                         p.n_items, p.n_slots, (int64_t)p.bytes};
+                         p.n_items, p.n_slots, (int64_t)p.bytes, p.n_fitems};
     for (int k = 0; k < cap && k < (int)(sizeof(v) / sizeof(v[0])); ++k) info[k] = v[k];
     return ok();
 }
@@ -549,8 +592,9 @@ radon_status_t radon_plan_stage_times(radon_plan_t plan, double* ms, int64_t* co
 int radon_stage_count(void) { return rn::ST_COUNT; }
 
 const char* radon_stage_name(int stage) {
-    static const char* names[rn::ST_COUNT] = {"F1_row_fft", "F2_col_fft", "F34_interp_ray_ifft", "A1_ray_fft",
-                                              "A2_spread", "A2_reduce", "A3_col_ifft", "A4_row_ifft"};
+    static const char* names[rn::ST_COUNT] = {"F1_row_fft", "F2_col_fft", "F3_interp", "F4_ray_ifft",
+                                              "A1_ray_fft", "A2_spread", "A2_reduce", "A3_col_ifft",
+                                              "A4_row_ifft"};
     return (stage >= 0 && stage < rn::ST_COUNT) ? names[stage] : "";
 }
 

@@ -1,5 +1,6 @@
 // radon_fwd.hip - launchers of the forward path (F1 row FFT, F2 column FFT,
-// F34 polar interpolation + ray inverse FFT), dispatched on the FFT length.
+// F3 tiled polar interpolation, F4 ray inverse FFT), dispatched on the FFT
+// length, kernel width and tile size.
 #include "radon_internal.hpp"
 
 namespace rn {
@@ -40,15 +41,41 @@ hipError_t launch_f2(const Plan& p, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int W, int T>
+static hipError_t launch_f3_wt(const Plan& p, hipStream_t st) {
+    if (p.n_fitems == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_f3_tiles<W, T, 256>), dim3(p.n_fitems), dim3(256), 0, st, p.fitems, p.perm, p.grid,
+                       p.cs, p.kbc, p.kbS, p.Xr, p.G, p.n_det, p.n_views);
+    return hipGetLastError();
+}
+
 template <int W>
-static hipError_t launch_f34_w(const Plan& p, float* sino, hipStream_t st) {
+static hipError_t launch_f3_w(const Plan& p, hipStream_t st) {
+    switch (p.T) {
+        case 8: return launch_f3_wt<W, 8>(p, st);
+        case 16: return launch_f3_wt<W, 16>(p, st);
+        case 32: return launch_f3_wt<W, 32>(p, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_f3(const Plan& p, hipStream_t st) {
+    switch (p.W) {
+        case 4: return launch_f3_w<4>(p, st);
+        case 6: return launch_f3_w<6>(p, st);
+        case 8: return launch_f3_w<8>(p, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_f4(const Plan& p, float* sino, hipStream_t st) {
     const dim3 grid((p.n_views + 1) / 2);
     switch (p.n_det) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = fft_threads(L, 2);                                                  \
-        hipLaunchKernelGGL((k_f34_rays<L, W, NT>), grid, dim3(NT), 0, st, p.grid, sino, p.cs,   \
-                           p.kbtab, p.kbL, p.tw_N, p.G, p.n_views);                            \
+        constexpr int NT = fft_threads(L, 1);                                                  \
+        hipLaunchKernelGGL((k_f4_rays<L, NT>), grid, dim3(NT), 0, st, p.Xr, sino, p.tw_N,       \
+                           p.n_views);                                                         \
         break;                                                                                 \
     }
         RN_FOR_LENGTHS(RN_CASE)
@@ -57,15 +84,6 @@ static hipError_t launch_f34_w(const Plan& p, float* sino, hipStream_t st) {
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-hipError_t launch_f34(const Plan& p, float* sino, hipStream_t st) {
-    switch (p.W) {
-        case 4: return launch_f34_w<4>(p, sino, st);
-        case 6: return launch_f34_w<6>(p, sino, st);
-        case 8: return launch_f34_w<8>(p, sino, st);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 }  // namespace rn

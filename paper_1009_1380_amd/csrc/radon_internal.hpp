@@ -20,7 +20,8 @@ namespace rn {
 enum Stage {
     ST_F1 = 0,
     ST_F2,
-    ST_F34,
+    ST_F3,
+    ST_F4,
     ST_A1,
     ST_A2,
     ST_A2R,
@@ -39,8 +40,10 @@ struct Plan {
     int n = 0, n_views = 0, n_det = 0, W = 0, G = 0, T = 0, ntl = 0;
     double sigma = 0, beta = 0;
     int64_t n_samples = 0;   // real samples + mirrored Nyquist samples
-    int n_bins = 0, n_items = 0, n_slots = 0, n_splits = 0;
-    float kbL = 0;
+    int n_bins = 0;                     // tiles; the sort has 4 edge classes per tile
+    int n_items = 0, n_slots = 0, n_splits = 0;   // spreading work
+    int n_fitems = 0;                   // forward interpolation work
+    float kbS = 0;                      // cubic pieces per unit of t
 
     // device tables
     double2* cs = nullptr;       // per view (cos, sin), float64
@@ -48,14 +51,16 @@ struct Plan {
     float2* shift_n = nullptr;   // e^{-i pi (i - n/2)/n}, n
     float2* tw_n = nullptr;      // e^{-2 pi i t/n}, n
     float2* tw_N = nullptr;      // e^{-2 pi i t/N}, N
-    float2* kbtab = nullptr;     // (phi, slope) per 1/L step on [0, W/2]
+    float4* kbc = nullptr;       // cubic pieces of phi on [0, W/2]
     // device workspace
     float2* T1 = nullptr;        // (n+1) x n complex64
     float2* grid = nullptr;      // (n+1) x G complex64
-    float2* Yh = nullptr;        // n_views x (N/2+1) complex64
+    float2* Yh = nullptr;        // n_views x (N/2+1) complex64 (adjoint ray spectra)
+    float2* Xr = nullptr;        // n_views x (N/2+1) complex64 (forward polar samples)
     int* perm = nullptr;         // sorted sample ids
-    int* offsets = nullptr;      // n_bins + 1
-    WorkItem* items = nullptr;
+    int* offs4 = nullptr;        // 4 * n_bins + 1 class starts
+    TileItem* fitems = nullptr;
+    TileItem* items = nullptr;
     SplitTile* splits = nullptr;
     float2* partials = nullptr;
     size_t bytes = 0;
@@ -71,7 +76,8 @@ struct Plan {
 // kernel launchers; each returns the launch status
 hipError_t launch_f1(const Plan& p, const float* img, hipStream_t st);
 hipError_t launch_f2(const Plan& p, hipStream_t st);
-hipError_t launch_f34(const Plan& p, float* sino, hipStream_t st);
+hipError_t launch_f3(const Plan& p, hipStream_t st);
+hipError_t launch_f4(const Plan& p, float* sino, hipStream_t st);
 hipError_t launch_a1(const Plan& p, const float* sino, hipStream_t st);
 hipError_t launch_a2(const Plan& p, hipStream_t st);
 hipError_t launch_a2_reduce(const Plan& p, hipStream_t st);

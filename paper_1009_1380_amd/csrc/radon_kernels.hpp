@@ -13,13 +13,13 @@
 //   forward  F1  image rows (pairs packed as one complex line) -> row FFT,
 //                split into real-input spectra, stored T1[mx][i]   (n+1 x n)
 //            F2  each T1 line -> column FFT -> grid[mx][my]       (n+1 x G)
-//            F34 per pair of rays: Kaiser-Bessel interpolation of the
-//                N/2+1 independent samples from the half grid, then a
-//                complex-to-real inverse FFT along the rays -> sinogram
+//            F3  per grid tile: Kaiser-Bessel interpolation, from an LDS copy
+//                of the tile, of the samples sorted into it -> Xr[a][|q|]
+//            F4  per pair of rays: complex-to-real inverse FFT -> sinogram
 //   adjoint  A1  per pair of rays: real-to-complex FFT -> Yh[a][q], q <= N/2
-//            A2  per output tile: deterministic spreading of the samples of
-//                the tile's four bins (sorted by footprint-origin tile) into
-//                an LDS accumulator, in a fixed order, no atomics
+//            A2  per output tile: deterministic spreading of the samples
+//                that reach the tile into an LDS accumulator, no atomics on
+//                floating-point data
 //            A3  each grid line -> inverse column FFT, keep n rows -> T1
 //            A4  pairs of image rows: complex-to-real inverse row FFT,
 //                keep n columns, deapodize -> image
@@ -38,16 +38,17 @@ namespace rn {
 
 // ---------------------------------------------------------------- helpers
 
-// Kaiser-Bessel weight phi(t) for t >= 0 from the (value, slope) table with
-// L entries per unit; strict support: 0 for t >= W/2.
-__device__ __forceinline__ float kb_weight(float t, const float2* __restrict__ tab, float L,
-                                           float half_w) {
+// Kaiser-Bessel weight phi(t) for t >= 0 from a table of cubic pieces, S
+// pieces per unit of t (c.x + c.y f + c.z f^2 + c.w f^3 on piece floor(t S),
+// f = frac(t S)); strict support: 0 for t >= W/2. S is a power of two, so
+// t * S is exact and the piece index stays below (W/2) S.
+__device__ __forceinline__ float kb_weight(float t, const float4* __restrict__ tab, float S, float half_w) {
     if (!(t < half_w)) return 0.0f;
-    float x = t * L;
-    int i = (int)x;
-    float f = x - (float)i;
-    float2 e = tab[i];
-    return fmaf(f, e.y, e.x);
+    const float x = t * S;
+    const int i = (int)x;
+    const float f = x - (float)i;
+    const float4 c = tab[i];
+    return fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
 }
 
 struct SampleGeom {
@@ -155,85 +156,153 @@ __global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, f
     }
 }
 
-// ---------------------------------------------------------------- F34
-// Two rays per workgroup. Samples q = 0..N/2-1 and q = -N/2 are interpolated
-// from the half grid (footprint points with mx mod G in (G/2, G) are read as
-// the conjugate of their mirror), then y = Re((1/N) IFFT) with the Hermitian
-// extension X[-q] = conj X[q]; the two real outputs share one complex IFFT.
-template <int ND, int W, int NT>
-__global__ __launch_bounds__(NT) void k_f34_rays(const float2* __restrict__ grid, float* __restrict__ sino,
-                                                const double2* __restrict__ cs,
-                                                const float2* __restrict__ kbtab, float kbL,
-                                                const float2* __restrict__ tw, int G, int n_views) {
+// ---------------------------------------------------------------- samples
+// Sample ids: 0..M-1 are the polar samples j = a*N + q + N/2 (M = n_views*N);
+// M..M+n_views-1 are the mirrored Nyquist samples (view a at q = +N/2).
+__device__ __forceinline__ void decode_sample(int v, int M, int ND, int& a, int& q) {
+    if (v < M) {
+        a = v / ND;
+        q = v - a * ND - ND / 2;
+    } else {
+        a = v - M;
+        q = ND / 2;
+    }
+}
+
+// Centred grid coordinate of the first footprint point: (floor - W/2 + 1 + G/2) mod G.
+__device__ __forceinline__ int footprint_origin(int b, int W, int G) { return mod_pos(b - W / 2 + 1 + G / 2, G); }
+
+// Tile columns whose samples the forward interpolates: the Hermitian half
+// plane mx in [0, G/2] (centred columns ntl/2..ntl-1 and column 0, which
+// holds mx = G/2) plus column ntl/2-1 (mx in [-T, 0)), so that footprints
+// straddling mx = 0 are taken whole.
+__device__ __forceinline__ bool forward_column(int cx, int ntl) { return cx == 0 || cx >= ntl / 2 - 1; }
+
+// Forward / spreading work item: a slice of the sorted samples of one tile.
+struct TileItem {
+    int cx, cy;      // tile, centred tile coordinates
+    int start;       // first position (forward: absolute in perm; spreading: visit index)
+    int count;       // number of samples / visits
+    int slot;        // spreading only: -1 writes the grid, else partial slot
+    int pad0, pad1, pad2;
+};
+
+// ---------------------------------------------------------------- F3
+// Kaiser-Bessel interpolation of the polar samples from the half-plane grid,
+// one tile per workgroup. The tile and its (W-1) halo are staged in LDS
+// (points with mx < 0 read as conjugates of their mirror, wrap mod G), then
+// every sample whose footprint origin is in the tile is interpolated from LDS.
+// Of each conjugate pair (q, -q) exactly one member is evaluated: q >= 0 when
+// its origin tile is a forward column, else -q (result conjugated); the pair
+// (-N/2, +N/2) likewise. Results go to Xr[a][t], t = |q| (t = N/2: Nyquist).
+template <int W, int T, int NT>
+__global__ __launch_bounds__(NT) void k_f3_tiles(const TileItem* __restrict__ items, const int* __restrict__ perm,
+                                                const float2* __restrict__ grid, const double2* __restrict__ cs,
+                                                const float4* __restrict__ kbc, float kbS,
+                                                float2* __restrict__ Xr, int G, int ND, int n_views) {
+    constexpr int P = T + W - 1;
+    __shared__ float2 tile[P * P];   // [lx][ly], lx along u (mx), ly along v (my)
+    const int tid = threadIdx.x;
+    const TileItem it = items[blockIdx.x];
+    const int x0 = it.cx * T, y0 = it.cy * T;
+    const int ntl = G / T;
+    const int M = n_views * ND;
+    const int HQ = ND / 2 + 1;
+    const float hw = 0.5f * (float)W;
+    for (int e = tid; e < P * P; e += NT) {
+        const int lx = e / P, ly = e - lx * P;
+        int mx = mod_pos(x0 + lx, G) - G / 2;        // in [-G/2, G/2)
+        const int my = mod_pos(y0 + ly, G) - G / 2;
+        if (mx == -G / 2) mx = G / 2;
+        float2 val;
+        if (mx >= 0) {
+            val = grid[(size_t)mx * G + mod_pos(my, G)];
+        } else {
+            val = cconj(grid[(size_t)(-mx) * G + mod_pos(-my, G)]);
+        }
+        tile[e] = val;
+    }
+    __syncthreads();
+    for (int k = tid; k < it.count; k += NT) {
+        const int v = perm[it.start + k];
+        int a, q;
+        decode_sample(v, M, ND, a, q);
+        const double2 csa = cs[a];
+        bool conj_out = false;
+        int t;
+        if (q == -ND / 2) { t = ND / 2; }
+        else if (q >= 0 && q < ND / 2) { t = q; }
+        else {
+            // a mirror: evaluated only if its canonical partner's origin tile
+            // is not a forward column
+            const int qc = (q == ND / 2) ? -ND / 2 : -q;
+            const SampleGeom gc = sample_geom(csa.x, csa.y, qc, G, ND);
+            if (forward_column(footprint_origin(gc.bu, W, G) / T, ntl)) continue;
+            t = (q == ND / 2) ? ND / 2 : -q;
+            conj_out = true;
+        }
+        const SampleGeom g = sample_geom(csa.x, csa.y, q, G, ND);
+        const int ox = footprint_origin(g.bu, W, G) - x0;
+        const int oy = footprint_origin(g.bv, W, G) - y0;
+        float wy[W];
+#pragma unroll
+        for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbc, kbS, hw);
+        const float2* src = tile + ox * P + oy;
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int al = 0; al < W; ++al) {
+            const float wx = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbc, kbS, hw);
+            float2 racc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int gm = 0; gm < W; ++gm) {
+                const float2 val = src[al * P + gm];
+                racc.x = fmaf(wy[gm], val.x, racc.x);
+                racc.y = fmaf(wy[gm], val.y, racc.y);
+            }
+            acc.x = fmaf(wx, racc.x, acc.x);
+            acc.y = fmaf(wx, racc.y, acc.y);
+        }
+        Xr[(size_t)a * HQ + t] = conj_out ? cconj(acc) : acc;
+    }
+}
+
+// ---------------------------------------------------------------- F4
+// Two rays per workgroup: y = Re((1/N) IFFT) of the Hermitian extension
+// X[-q] = conj X[q] of Xr (bins 0 and N/2 taken as real); the two real
+// outputs share one complex IFFT. Output bin d is s = d - N/2 at s mod N.
+template <int ND, int NT>
+__global__ __launch_bounds__(NT) void k_f4_rays(const float2* __restrict__ Xr, float* __restrict__ sino,
+                                               const float2* __restrict__ tw, int n_views) {
     constexpr int HQ = ND / 2 + 1;
-    __shared__ float2 xs[2 * HQ];
     __shared__ float2 lds[ND];
     const int tid = threadIdx.x;
     const int a0 = blockIdx.x * 2;
-    const float hw = 0.5f * (float)W;
-    for (int sidx = tid; sidx < 2 * HQ; sidx += NT) {
-        const int r = sidx / HQ;
-        const int t = sidx - r * HQ;
-        const int a = a0 + r;
-        float2 acc = make_float2(0.f, 0.f);
-        if (a < n_views) {
-            const int q = (t < ND / 2) ? t : -(ND / 2);
-            const double2 csa = cs[a];
-            const SampleGeom g = sample_geom(csa.x, csa.y, q, G, ND);
-            float wy[W];
-#pragma unroll
-            for (int gm = 0; gm < W; ++gm) {
-                const float tt = g.fv + (float)(W / 2 - 1 - gm);
-                wy[gm] = kb_weight(fabsf(tt), kbtab, kbL, hw);
-            }
-#pragma unroll
-            for (int al = 0; al < W; ++al) {
-                const float tt = g.fu + (float)(W / 2 - 1 - al);
-                const float wx = kb_weight(fabsf(tt), kbtab, kbL, hw);
-                int mw = mod_pos(g.bu - W / 2 + 1 + al, G);
-                if (mw > G / 2) mw -= G;
-                const bool mir = mw < 0;
-                const float2* line = grid + (size_t)(mir ? -mw : mw) * G;
-                float2 racc = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int gm = 0; gm < W; ++gm) {
-                    const int my = g.bv - W / 2 + 1 + gm;
-                    const int row = mod_pos(mir ? -my : my, G);
-                    const float2 val = line[row];
-                    racc.x = fmaf(wy[gm], val.x, racc.x);
-                    racc.y = fmaf(wy[gm], mir ? -val.y : val.y, racc.y);
-                }
-                acc.x = fmaf(wx, racc.x, acc.x);
-                acc.y = fmaf(wx, racc.y, acc.y);
-            }
-        }
-        xs[sidx] = acc;
-    }
-    __syncthreads();
-    // Z = A + i B with A, B the Hermitian extensions of the two rays; store
-    // conj(Z) so the forward engine yields conj of the inverse transform.
+    const bool has_b = a0 + 1 < n_views;
+    const float2* xa = Xr + (size_t)a0 * HQ;
+    const float2* xb = Xr + (size_t)(a0 + 1) * HQ;
+    const float2 zero = make_float2(0.f, 0.f);
+    // Z = A + i B, stored conjugated so the forward engine gives conj(IFFT)
     for (int q = tid; q < ND; q += NT) {
         float2 A, B;
         if (q == 0 || q == ND / 2) {
-            A = make_float2(xs[q].x, 0.f);
-            B = make_float2(xs[HQ + q].x, 0.f);
+            A = make_float2(xa[q].x, 0.f);
+            B = has_b ? make_float2(xb[q].x, 0.f) : zero;
         } else if (q < ND / 2) {
-            A = xs[q];
-            B = xs[HQ + q];
+            A = xa[q];
+            B = has_b ? xb[q] : zero;
         } else {
-            A = cconj(xs[ND - q]);
-            B = cconj(xs[HQ + ND - q]);
+            A = cconj(xa[ND - q]);
+            B = has_b ? cconj(xb[ND - q]) : zero;
         }
-        const float2 z = make_float2(A.x - B.y, A.y + B.x);
-        lds[q] = cconj(z);
+        lds[q] = make_float2(A.x - B.y, -(A.y + B.x));
     }
     __syncthreads();
     fft_lds<ND, 1, NT>(lds, tw, tid);
     const float inv = 1.0f / (float)ND;
     for (int d = tid; d < ND; d += NT) {
         const float2 z = cconj(lds[(d + ND / 2) % ND]);
-        if (a0 < n_views) sino[(size_t)a0 * ND + d] = z.x * inv;
-        if (a0 + 1 < n_views) sino[(size_t)(a0 + 1) * ND + d] = z.y * inv;
+        sino[(size_t)a0 * ND + d] = z.x * inv;
+        if (has_b) sino[(size_t)(a0 + 1) * ND + d] = z.y * inv;
     }
 }
 
@@ -267,123 +336,125 @@ __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, 
 }
 
 // ---------------------------------------------------------------- A2
-// Deterministic binned spreading. One wave per work item; a work item is a
-// contiguous slice of the visit list of one output tile (cx, cy) of the
-// centred tile grid, where the visit list is the concatenation of the
-// sorted samples of bins (cx-1,cy-1), (cx,cy-1), (cx-1,cy), (cx,cy).
-// Each visited sample is staged (local footprint origin, W x-weights,
-// W values Y*wy) by one lane, then the wave applies the staged samples one
-// after another, lane = footprint point, into a T x T LDS accumulator. The
-// order of additions is fixed, so results are bitwise reproducible.
-struct WorkItem {
-    int cx, cy;      // output tile, centred tile coordinates
-    int start;       // first visit index
-    int count;       // number of visits
-    int slot;        // -1: write the grid; else partial slot
-    int pad0, pad1, pad2;
-};
-
+// Deterministic binned spreading, one wave per work item (a slice of one
+// output tile's visit list). The visit list of tile (cx, cy) is the
+// concatenation of: the diagonal neighbour bin's class 2, the v-neighbour
+// bin's classes 2-3, the u-neighbour bin's classes 1-2 and the own bin (all
+// classes) -- exactly the samples whose footprint reaches the tile.
+//
+// Lane l takes visits l*S .. l*S+S-1 (S = ceil(count/64)), one per round. In
+// a round each lane computes its sample's W x-weights and W values Y*wy, then
+// adds its W x W footprint into a halo'd LDS accumulator, one footprint point
+// per instruction. Lanes whose footprint origins coincide would collide, so
+// a round runs in sub-rounds: the lowest pending lane of each origin cell
+// (claimed with an integer atomic min, deterministic) adds, the others wait.
+// Every grid value is therefore accumulated in one fixed order.
 template <int W, int T>
-__global__ __launch_bounds__(64) void k_a2_spread(const WorkItem* __restrict__ items,
-                                                 const int* __restrict__ offsets,
-                                                 const int* __restrict__ perm,
-                                                 const float2* __restrict__ Yh,
-                                                 const double2* __restrict__ cs,
-                                                 const float2* __restrict__ kbtab, float kbL,
+__global__ __launch_bounds__(64) void k_a2_spread(const TileItem* __restrict__ items,
+                                                 const int* __restrict__ offs4, const int* __restrict__ perm,
+                                                 const float2* __restrict__ Yh, const double2* __restrict__ cs,
+                                                 const float4* __restrict__ kbc, float kbS,
                                                  float2* __restrict__ grid, float2* __restrict__ partials,
                                                  int G, int ND, int n_views) {
-    struct Staged {
-        int ox, oy;
-        float wx[W];
-        float2 ywy[W];
-    };
-    __shared__ float2 acc[T * T];
-    __shared__ Staged st[64];
+    constexpr int P = T + 2 * (W - 1);   // accumulator side: local [-(W-1), T+W-1)
+    constexpr int C = T + W - 1;         // origin cells: local [-(W-1), T)
+    constexpr int FREE = 64;
+    __shared__ float2 acc[P * P];
+    __shared__ int owner[C * C];
     const int lane = threadIdx.x;
-    const WorkItem it = items[blockIdx.x];
-    const int NTL = G / T;
+    const TileItem it = items[blockIdx.x];
+    const int ntl = G / T;
     const int M = n_views * ND;
     const int HQ = ND / 2 + 1;
     const float hw = 0.5f * (float)W;
 
-    for (int e = lane; e < T * T; e += 64) acc[e] = make_float2(0.f, 0.f);
+    for (int e = lane; e < P * P; e += 64) acc[e] = make_float2(0.f, 0.f);
+    for (int e = lane; e < C * C; e += 64) owner[e] = FREE;
 
-    // visit ranges of the four bins: up-left, up, left, own
-    const int xl = (it.cx + NTL - 1) % NTL, yu = (it.cy + NTL - 1) % NTL;
-    const int b0 = yu * NTL + xl, b1 = yu * NTL + it.cx, b2 = it.cy * NTL + xl, b3 = it.cy * NTL + it.cx;
-    const int rs0 = offsets[b0], rl0 = offsets[b0 + 1] - rs0;
-    const int rs1 = offsets[b1], rl1 = offsets[b1 + 1] - rs1;
-    const int rs2 = offsets[b2], rl2 = offsets[b2 + 1] - rs2;
-    const int rs3 = offsets[b3];
-    const int x0 = it.cx * T, y0 = it.cy * T;   // tile origin, centred coordinates
+    const int xl = (it.cx + ntl - 1) % ntl, yu = (it.cy + ntl - 1) % ntl;
+    const int b_ul = yu * ntl + xl, b_u = yu * ntl + it.cx, b_l = it.cy * ntl + xl, b_o = it.cy * ntl + it.cx;
+    const int s0 = offs4[4 * b_ul + 2], n0 = offs4[4 * b_ul + 3] - s0;
+    const int s1 = offs4[4 * b_u + 2], n1 = offs4[4 * b_u + 4] - s1;
+    const int s2 = offs4[4 * b_l + 1], n2 = offs4[4 * b_l + 3] - s2;
+    const int s3 = offs4[4 * b_o];
+    const int x0 = it.cx * T, y0 = it.cy * T;
     const int xvalid = (it.cx == 0) ? 1 : T;   // tile column 0 holds only mx = G/2
+    const int S = (it.count + 63) / 64;
     __syncthreads();
 
-    for (int base = 0; base < it.count; base += 64) {
-        const int nv = min(64, it.count - base);
-        if (lane < nv) {
-            int t = it.start + base + lane;
-            int pos;
-            if (t < rl0) pos = rs0 + t;
-            else if ((t -= rl0) < rl1) pos = rs1 + t;
-            else if ((t -= rl1) < rl2) pos = rs2 + t;
-            else pos = rs3 + (t - rl2);
+    for (int r = 0; r < S; ++r) {
+        const int t = lane * S + r;
+        bool pending = t < it.count;
+        int base = 0, cell = 0;
+        float wx[W];
+        float2 ywy[W];
+        if (pending) {
+            int u = it.start + t, pos;
+            if (u < n0) pos = s0 + u;
+            else if ((u -= n0) < n1) pos = s1 + u;
+            else if ((u -= n1) < n2) pos = s2 + u;
+            else pos = s3 + (u - n2);
             const int v = perm[pos];
             int a, q;
+            decode_sample(v, M, ND, a, q);
             float2 Y;
-            if (v < M) {
-                a = v / ND;
-                q = v - a * ND - ND / 2;
-                if (q >= 0) Y = Yh[(size_t)a * HQ + q];
-                else if (q > -ND / 2) Y = cconj(Yh[(size_t)a * HQ - q]);
-                else Y = Yh[(size_t)a * HQ + ND / 2];
-            } else {
-                a = v - M;
-                q = ND / 2;
-                Y = Yh[(size_t)a * HQ + ND / 2];
-            }
+            if (q >= 0 && q < ND / 2) Y = Yh[(size_t)a * HQ + q];
+            else if (q < 0 && q > -ND / 2) Y = cconj(Yh[(size_t)a * HQ - q]);
+            else Y = Yh[(size_t)a * HQ + ND / 2];
             const double2 csa = cs[a];
             const SampleGeom g = sample_geom(csa.x, csa.y, q, G, ND);
-            int ox = mod_pos(g.bu - W / 2 + 1 + G / 2, G) - x0;
-            int oy = mod_pos(g.bv - W / 2 + 1 + G / 2, G) - y0;
+            int ox = footprint_origin(g.bu, W, G) - x0;
+            int oy = footprint_origin(g.bv, W, G) - y0;
             if (ox >= G / 2) ox -= G;
             if (ox < -G / 2) ox += G;
             if (oy >= G / 2) oy -= G;
             if (oy < -G / 2) oy += G;
-            st[lane].ox = ox;
-            st[lane].oy = oy;
+            base = (ox + W - 1) * P + (oy + W - 1);
+            cell = (ox + W - 1) * C + (oy + W - 1);
 #pragma unroll
-            for (int al = 0; al < W; ++al)
-                st[lane].wx[al] = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbtab, kbL, hw);
+            for (int al = 0; al < W; ++al) wx[al] = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbc, kbS, hw);
 #pragma unroll
             for (int gm = 0; gm < W; ++gm) {
-                const float wy = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbtab, kbL, hw);
-                st[lane].ywy[gm] = make_float2(Y.x * wy, Y.y * wy);
+                const float wy = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbc, kbS, hw);
+                ywy[gm] = make_float2(Y.x * wy, Y.y * wy);
             }
         }
-        __syncthreads();
-        const int al = lane % W, gm = lane / W;
-        for (int s = 0; s < nv; ++s) {
-            if (lane < W * W) {
-                const int lx = st[s].ox + al;
-                const int ly = st[s].oy + gm;
-                if (lx >= 0 && lx < xvalid && ly >= 0 && ly < T) {
-                    const float w = st[s].wx[al];
-                    const float2 c = st[s].ywy[gm];
-                    float2 o = acc[lx * T + ly];
-                    o.x = fmaf(w, c.x, o.x);
-                    o.y = fmaf(w, c.y, o.y);
-                    acc[lx * T + ly] = o;
+        while (__ballot(pending) != 0) {
+            if (pending) atomicMin(&owner[cell], lane);
+            __builtin_amdgcn_wave_barrier();
+            const bool win = pending && __hip_atomic_load(&owner[cell], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP) == lane;
+            if (win) {
+                // One footprint point per step. Winners have distinct origin
+                // cells, so within a step every lane touches its own address,
+                // but step k of one lane may hit the address of step j of
+                // another: the compiler barrier keeps each step's read after
+                // the previous step's write (the LDS executes a wave's
+                // instructions in order).
+                float2* dst = acc + base;
+#pragma unroll
+                for (int al = 0; al < W; ++al) {
+#pragma unroll
+                    for (int gm = 0; gm < W; ++gm) {
+                        float2 o = dst[al * P + gm];
+                        o.x = fmaf(wx[al], ywy[gm].x, o.x);
+                        o.y = fmaf(wx[al], ywy[gm].y, o.y);
+                        dst[al * P + gm] = o;
+                        asm volatile("" ::: "memory");
+                    }
                 }
+                __hip_atomic_store(&owner[cell], FREE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            __syncthreads();
+            pending = pending && !win;
+            __builtin_amdgcn_wave_barrier();
         }
     }
+    __syncthreads();
     // write out: local (lx, ly) -> mx = (x0 + lx - G/2) mod G, my = (y0 + ly - G/2) mod G
     const int my0 = mod_pos(y0 - G / 2, G);
     for (int e = lane; e < xvalid * T; e += 64) {
         const int lx = e / T, ly = e - lx * T;
-        const float2 val = acc[e];
+        const float2 val = acc[(lx + W - 1) * P + (ly + W - 1)];
         if (it.slot < 0) {
             const int mx = mod_pos(x0 + lx - G / 2, G);
             grid[(size_t)mx * G + my0 + ly] = val;

@@ -5,7 +5,8 @@
 // Here the bins are uniform T x T tiles of the centred oversampled grid,
 // keyed by the tile of each sample's footprint origin:
 //   o = (floor(u) - W/2 + 1 + G/2) mod G,  key = (o_v div T)(G/T) + (o_u div T),
-// and the samples are stably sorted by key (ties in increasing sample id).
+// refined by the footprint's edge class, and the samples are stably sorted by
+// the refined key (ties in increasing sample id).
 // All integer work: the result is bit-exact and deterministic.
 #pragma once
 
@@ -20,8 +21,10 @@ constexpr int SORT_IPT = 16;
 constexpr int SORT_TILE = SORT_NT * SORT_IPT;   // elements per block
 constexpr int SORT_RADIX = 16;                  // 4-bit digits
 
-// Sample ids 0..M-1 are the real samples j = a*N + q + N/2; ids M..M+n_views-1
-// are the mirrored Nyquist samples (view a at q = +N/2).
+// Refined key of every sample: 4 * (tile of the footprint origin) + edge
+// class (0: footprint inside the tile, 1: crosses the u edge only, 2: both,
+// 3: the v edge only). Sample ids 0..M-1 are the polar samples
+// j = a*N + q + N/2; ids M..M+n_views-1 are the mirrored Nyquist samples.
 __global__ __launch_bounds__(256) void k_sample_keys(const double2* __restrict__ cs, int* __restrict__ keys,
                                                     int* __restrict__ ids, int n_views, int ND, int G,
                                                     int W, int T) {
@@ -30,13 +33,15 @@ __global__ __launch_bounds__(256) void k_sample_keys(const double2* __restrict__
     const int v = blockIdx.x * 256 + threadIdx.x;
     if (v >= total) return;
     int a, q;
-    if (v < M) { a = v / ND; q = v - a * ND - ND / 2; }
-    else { a = v - M; q = ND / 2; }
+    decode_sample(v, M, ND, a, q);
     const double2 c = cs[a];
     const SampleGeom g = sample_geom(c.x, c.y, q, G, ND);
-    const int ou = mod_pos(g.bu - W / 2 + 1 + G / 2, G);
-    const int ov = mod_pos(g.bv - W / 2 + 1 + G / 2, G);
-    keys[v] = (ov / T) * (G / T) + (ou / T);
+    const int ou = footprint_origin(g.bu, W, G);
+    const int ov = footprint_origin(g.bv, W, G);
+    const bool cu = (ou % T) + W - 1 >= T;
+    const bool cv = (ov % T) + W - 1 >= T;
+    const int cls = (cu && cv) ? 2 : (cu ? 1 : (cv ? 3 : 0));
+    keys[v] = 4 * ((ov / T) * (G / T) + (ou / T)) + cls;
     ids[v] = v;
 }
 

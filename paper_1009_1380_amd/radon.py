@@ -137,7 +137,7 @@ class Plan:
     """
 
     INFO_KEYS = ("n", "n_views", "n_det", "W", "G", "T", "n_samples", "n_bins",
-                 "n_items", "n_slots", "device_bytes")
+                 "n_items", "n_slots", "device_bytes", "n_fitems")
 
     def __init__(self, n: int, angles, n_det: int, sigma: float = 2.0, W: int = 6):
         ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).ravel())
@@ -216,7 +216,7 @@ class Plan:
     def sort_indices(self):
         inf = self.info()
         perm = np.empty(inf["n_samples"], dtype=np.int32)
-        offs = np.empty(inf["n_bins"] + 1, dtype=np.int32)
+        offs = np.empty(4 * inf["n_bins"] + 1, dtype=np.int32)
         _check(lib().radon_plan_sort_indices(self._h, perm.ctypes.data_as(ctypes.c_void_p), perm.size,
                                              offs.ctypes.data_as(ctypes.c_void_p), offs.size),
                "radon_plan_sort_indices")

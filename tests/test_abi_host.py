@@ -37,7 +37,7 @@ def test_supported_lengths():
 
 def test_stage_names():
     names = rb.stage_names()
-    assert names[0] == "F1_row_fft" and "A2_spread" in names and len(names) == 8
+    assert names[0] == "F1_row_fft" and "A2_spread" in names and "F3_interp" in names and len(names) == 9
 
 
 def _plan_status(n, nv, n_det, sigma, W, angles="ok"):

@@ -14,7 +14,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.binning import bin_offsets, sample_keys, stable_sort  # noqa: E402
+from oracle.binning import bin_offsets, refined_keys, sample_keys, stable_sort  # noqa: E402
 from oracle.exact import radon_exact, radon_exact_adjoint  # noqa: E402
 from oracle.geometry import polar_uv, ray_q  # noqa: E402
 from oracle.grid import (GridParams, grid_adjoint, grid_fft2, grid_forward,  # noqa: E402
@@ -77,33 +77,40 @@ def test_fft_engine_vs_numpy(length):
 
 # ------------------------------------------------------------------ sort
 
-def extended_keys(angles, n, n_det, W, T):
+def extended_keys(angles, n, n_det, W, T, refined=True):
     """Oracle keys of the plan's samples: the n_views*n_det polar samples, then
     one mirrored Nyquist sample (q = +N/2) per view."""
     G = 2 * n
+    fn = refined_keys if refined else sample_keys
     u, v = polar_uv(angles, n_det, G)
     um, vm = polar_uv(angles, n_det, G, q=np.array([n_det // 2]))
-    k = sample_keys(u, v, G, W, T).ravel()
-    km = sample_keys(um, vm, G, W, T).ravel()
-    return np.concatenate([k, km])
+    return np.concatenate([fn(u, v, G, W, T).ravel(), fn(um, vm, G, W, T).ravel()])
 
 
-@pytest.mark.parametrize("n,n_det,nv", [(16, 16, 12), (32, 40, 33), (128, 128, 180), (64, 96, 7)])
+@pytest.mark.parametrize("n,n_det,nv", [(16, 16, 12), (32, 40, 33), (128, 128, 180), (64, 96, 7),
+                                        (2560, 2560, 1024)])
 def test_sort_bit_exact(n, n_det, nv):
-    """G10: perm and bin offsets equal the oracle's stable argsort / counts."""
+    """G10: perm and class offsets equal the oracle's stable argsort / counts
+    of the refined keys; the tile bins hold exactly the oracle's tile keys."""
     note(f"sort n={n} n_det={n_det} nv={nv}")
-    ang = special_angles(nv, 3) if nv != 180 else uniform_angles(nv)
+    ang = special_angles(nv, 3) if nv not in (180, 1024) else uniform_angles(nv)
     plan = Plan(n, ang, n_det)
     info = plan.info()
     perm, offs = plan.sort_indices()
-    keys = extended_keys(ang, n, n_det, plan.W, info["T"])
+    T = info["T"]
+    keys = extended_keys(ang, n, n_det, plan.W, T)
     assert perm.size == keys.size == info["n_samples"]
     assert np.array_equal(perm, stable_sort(keys).astype(np.int32))
-    assert np.array_equal(offs, bin_offsets(keys, info["n_bins"]).astype(np.int32))
-    # the real samples alone keep the order of the plain stable sort
+    assert np.array_equal(offs, bin_offsets(keys, 4 * info["n_bins"]).astype(np.int32))
+    # tile bins (every 4th offset) hold exactly the samples of each tile key
+    tkeys = extended_keys(ang, n, n_det, plan.W, T, refined=False)
+    assert np.array_equal(offs[::4], bin_offsets(tkeys, info["n_bins"]).astype(np.int32))
+    # within a class run the real samples keep increasing id
     M = nv * n_det
-    real = perm[perm < M]
-    assert np.array_equal(real, stable_sort(keys[:M]).astype(np.int32))
+    assert np.all(np.diff(keys[perm]) >= 0)
+    same = np.diff(keys[perm]) == 0
+    assert np.all(np.diff(perm)[same] > 0)
+    assert perm[perm >= M].size == nv
 
 
 # ------------------------------------------------------------------ kernel-level grids
@@ -270,7 +277,7 @@ def test_stream_and_profiling():
     s.synchronize()
     assert torch.equal(y, ref)
     times = plan.stage_times()
-    assert times["F1_row_fft"][1] == 1 and times["A2_spread"][1] == 1
+    assert times["F1_row_fft"][1] == 1 and times["F3_interp"][1] == 1 and times["A2_spread"][1] == 1
     assert all(ms >= 0 for ms, _ in times.values())
     plan.set_profiling(False)
     assert torch.isfinite(a).all()

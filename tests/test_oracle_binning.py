@@ -12,7 +12,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle.binning import bin_offsets, sample_keys, stable_sort
+from oracle.binning import bin_offsets, edge_class, refined_keys, sample_keys, stable_sort
 from oracle.geometry import angle_cos_sin, polar_uv, ray_q
 from radon_inputs import uniform_angles
 
@@ -63,3 +63,27 @@ def test_geometry_uses_one_multiply_per_coordinate():
     assert c[2] > 0 and c[2] < 1e-16
     q = ray_q(N)
     assert np.all(np.floor(u[2][q > 0]) == 0) and np.all(np.floor(u[2][q < 0]) == -1)
+
+
+@pytest.mark.parametrize("n,N,nv,T", [(16, 16, 12, 8), (32, 24, 20, 16), (64, 64, 30, 32)])
+def test_edge_class_matches_tiles_touched(n, N, nv, T):
+    """Brute force: the class says exactly which neighbouring tiles the
+    footprint reaches (class 0: own only; 1: +u; 3: +v; 2: +u, +v and diagonal)."""
+    G, W = 2 * n, 6
+    u, v = polar_uv(uniform_angles(nv), N, G)
+    cls = edge_class(u, v, G, W, T)
+    keys = sample_keys(u, v, G, W, T)
+    rk = refined_keys(u, v, G, W, T)
+    assert np.array_equal(rk, 4 * keys + cls)
+    nt = G // T
+    for uu, vv, c, k in zip(u.ravel(), v.ravel(), cls.ravel(), keys.ravel()):
+        tx, ty = int(k) % nt, int(k) // nt
+        touched = set()
+        for a in range(-W // 2 + 1, W // 2 + 1):
+            for g in range(-W // 2 + 1, W // 2 + 1):
+                cx = ((math.floor(uu) + a + G // 2) % G) // T
+                cy = ((math.floor(vv) + g + G // 2) % G) // T
+                touched.add(((cx - tx) % nt, (cy - ty) % nt))
+        expect = {0: {(0, 0)}, 1: {(0, 0), (1, 0)}, 3: {(0, 0), (0, 1)},
+                  2: {(0, 0), (1, 0), (0, 1), (1, 1)}}[int(c)]
+        assert touched == expect
