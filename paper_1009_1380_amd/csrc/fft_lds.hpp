@@ -8,8 +8,9 @@
 // registers, barriers, applies twiddles and the radix-R DFT, writes the
 // outputs back in place, and barriers again; no scratch buffer is needed.
 // Twiddles come from a float32 table e^{-2 pi i t/LEN}, t < LEN, built in
-// float64 on the host. The engine computes the forward (e^-) transform; the
-// callers obtain inverse transforms as conj(FFT(conj(x))).
+// float64 on the host (one entry per butterfly; the other powers are formed
+// by products). The engine computes the forward (e^-) transform; the callers
+// obtain inverse transforms as conj(FFT(conj(x))).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -132,9 +133,31 @@ constexpr RadixPlan make_plan(int len) {
 
 constexpr bool length_ok(int len) { return len >= 2 && make_plan(len).np > 0; }
 
+// LDS layout of one line of length LEN: element i lives at i + i/32 (one pad
+// slot per 32 elements, so strided butterfly writes spread over the banks);
+// lines are LDS_LS(LEN) elements apart.
+constexpr int lds_ls(int len) { return len + (len >> 5) + 1; }
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+
+// Twiddles w^m, m = 1..R-1, from w = w^1 by a shallow product tree (at most
+// three roundings deep), so each butterfly loads a single table entry.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 w1, float2* w) {
+    w[1] = w1;
+    if constexpr (R >= 3) w[2] = cmul(w1, w1);
+    if constexpr (R >= 4) w[3] = cmul(w[2], w1);
+    if constexpr (R >= 5) w[4] = cmul(w[2], w[2]);
+    if constexpr (R >= 8) {
+        w[5] = cmul(w[4], w1);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+    }
+}
+
 // One Stockham pass of radix R over B lines (line b at buf + b*LS), sub-length L.
 template <int LEN, int R, int L, int B, int NT, int LS>
 __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw, int tid) {
+    static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 8, "radix");
     constexpr int NB = LEN / R;                 // butterflies per line
     constexpr int TOT = NB * B;
     constexpr int IT = (TOT + NT - 1) / NT;
@@ -146,9 +169,9 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
         if (FULL || b < TOT) {
             const int line = b / NB;
             const int bf = b - line * NB;
-            const float2* src = buf + line * LS + bf;
+            const float2* src = buf + line * LS;
 #pragma unroll
-            for (int m = 0; m < R; ++m) v[it][m] = src[m * NB];
+            for (int m = 0; m < R; ++m) v[it][m] = src[lds_pad(bf + m * NB)];
         }
     }
     __syncthreads();
@@ -162,13 +185,16 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             const int k = bf / L;
             if constexpr (L > 1) {
                 constexpr int STEP = LEN / (L * R);
+                float2 w[R];
+                twiddle_powers<R>(tw[j * STEP], w);
 #pragma unroll
-                for (int m = 1; m < R; ++m) v[it][m] = cmul(v[it][m], tw[j * m * STEP]);
+                for (int m = 1; m < R; ++m) v[it][m] = cmul(v[it][m], w[m]);
             }
             Dft<R>::run(v[it]);
-            float2* dst = buf + line * LS + k * (L * R) + j;
+            float2* dst = buf + line * LS;
+            const int o = k * (L * R) + j;
 #pragma unroll
-            for (int m = 0; m < R; ++m) dst[m * L] = v[it][m];
+            for (int m = 0; m < R; ++m) dst[lds_pad(o + m * L)] = v[it][m];
         }
     }
     __syncthreads();
@@ -184,18 +210,23 @@ __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict
     }
 }
 
-// Forward FFT of B lines of length LEN in LDS (line b at buf + b*LS).
-// All NT threads of the workgroup must call it; the caller barriers before.
-template <int LEN, int B, int NT, int LS = LEN>
+// Forward FFT of B lines of length LEN in LDS (line b at buf + b*lds_ls(LEN),
+// element i at lds_pad(i)). All NT threads of the workgroup must call it; the
+// caller barriers before.
+template <int LEN, int B, int NT>
 __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ tw, int tid) {
     static_assert(length_ok(LEN), "FFT length must be 2^a 3^b 5^c");
-    fft_passes<LEN, 0, 1, B, NT, LS>(buf, tw, tid);
+    fft_passes<LEN, 0, 1, B, NT, lds_ls(LEN)>(buf, tw, tid);
 }
 
 // Threads per workgroup used for a transform of B lines of length LEN.
+// Threads for the row/column kernels, whose per-thread register arrays shrink
+// with more threads: 512 from length 1024 on.
+constexpr int line_threads(int len) { return len >= 1024 ? 512 : (len >= 256 ? 256 : (len >= 64 ? 128 : 64)); }
+
 constexpr int fft_threads(int len, int b) {
     int work = len * b / 8;
-    return work >= 256 ? 256 : (work >= 128 ? 128 : 64);
+    return work >= 1024 ? 512 : (work >= 256 ? 256 : (work >= 128 ? 128 : 64));
 }
 
 }  // namespace rn

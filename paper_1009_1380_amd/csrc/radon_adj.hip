@@ -26,7 +26,7 @@ hipError_t launch_a1(const Plan& p, const float* sino, hipStream_t st) {
 template <int W, int T>
 static hipError_t launch_a2_wt(const Plan& p, hipStream_t st) {
     if (p.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_a2_spread<W, T>), dim3(p.n_items), dim3(64), 0, st, p.items, p.offs4,
+    hipLaunchKernelGGL((k_a2_spread<W, T>), dim3(p.n_items), dim3(A2_NT), 0, st, p.items, p.offs4,
                        p.perm, p.Yh, p.cs, p.kbc, p.kbS, p.grid, p.partials, p.G, p.n_det,
                        p.n_views);
     return hipGetLastError();
@@ -67,7 +67,7 @@ hipError_t launch_a3(const Plan& p, hipStream_t st) {
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = fft_threads(L, 2);                                                  \
+        constexpr int NT = line_threads(L);                                                  \
         hipLaunchKernelGGL((k_a3_cols<L, NT>), grid, dim3(NT), 0, st, p.grid, p.T1, p.shift_n,  \
                            p.tw_n);                                                            \
         break;                                                                                 \
@@ -85,7 +85,7 @@ hipError_t launch_a4(const Plan& p, float* img, hipStream_t st) {
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = fft_threads(L, 4);                                                  \
+        constexpr int NT = line_threads(L);                                                  \
         hipLaunchKernelGGL((k_a4_rows<L, NT>), grid, dim3(NT), 0, st, p.T1, img, p.psi_inv,     \
                            p.shift_n, p.tw_n);                                                 \
         break;                                                                                 \

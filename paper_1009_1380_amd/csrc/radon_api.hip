@@ -42,7 +42,7 @@ radon_status_t ok() {
 
 // Visits per spreading work item; longer tile lists are split and their
 // partial tiles summed in a fixed order.
-constexpr int kA2Chunk = 1024;
+constexpr int kA2Chunk = rn::A2_MAX_VISITS;
 // Samples per forward interpolation work item.
 constexpr int kF3Chunk = 2048;
 // Cubic Kaiser-Bessel pieces per unit of t (a power of two).
@@ -260,25 +260,22 @@ radon_status_t sort_samples(Plan& p, std::vector<int>& offsets_host) {
 // tile of the half plane (tile column 0 holds the mx = G/2 line, columns
 // ntl/2..ntl-1 hold mx = 0..G/2-1); the visit list is the diagonal
 // neighbour's class 2, the v-neighbour's classes 2-3, the u-neighbour's
-// classes 1-2 and all of the own bin. Forward: one item per chunk of the own
-// bin of every forward tile (columns 0 and ntl/2-1..ntl-1).
+// classes 1-2 and all of the own bin. Forward: the forward tile columns
+// ntl/2-1, .., ntl-1, 0 are taken in consecutive pairs (the last pair wraps
+// to column 0) and the rows in pairs; each 2 x 2 super-tile's samples are
+// cut into items of at most kF3Chunk.
 radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
     const int ntl = p.ntl;
     auto run = [&](int bin, int c0, int c1) { return o4[4 * bin + c1] - o4[4 * bin + c0]; };
-    std::vector<rn::TileItem> items, fitems;
+    std::vector<rn::TileItem> items;
+    std::vector<rn::F3Item> fitems;
     std::vector<rn::SplitTile> splits;
     int slots = 0;
     for (int cy = 0; cy < ntl; ++cy) {
         for (int cx = 0; cx < ntl; ++cx) {
             const bool half = (cx == 0) || (cx >= ntl / 2);
-            const bool fwd = (cx == 0) || (cx >= ntl / 2 - 1);
-            const int own = cy * ntl + cx;
-            if (fwd) {
-                const int n_own = run(own, 0, 4);
-                for (int k = 0; k < n_own; k += kF3Chunk)
-                    fitems.push_back({cx, cy, o4[4 * own] + k, std::min(kF3Chunk, n_own - k), -1, 0, 0, 0});
-            }
             if (!half) continue;
+            const int own = cy * ntl + cx;
             const int xl = (cx + ntl - 1) % ntl, yu = (cy + ntl - 1) % ntl;
             const int total = run(yu * ntl + xl, 2, 3) + run(yu * ntl + cx, 2, 4) + run(cy * ntl + xl, 1, 3) +
                               run(own, 0, 4);
@@ -294,10 +291,29 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
             }
         }
     }
+    // forward columns in order, without repeats
+    std::vector<int> fcols;
+    for (int cx = std::max(ntl / 2 - 1, 0); cx < ntl; ++cx) fcols.push_back(cx);
+    if (std::find(fcols.begin(), fcols.end(), 0) == fcols.end()) fcols.push_back(0);
+    for (size_t k = 0; k < fcols.size(); k += 2) {
+        const int cx = fcols[k];
+        const int nbx = (k + 1 < fcols.size()) ? 2 : 1;
+        for (int cy = 0; cy < ntl; cy += 2) {
+            const int cy1 = (cy + 1) % ntl;
+            int n_all = run(cy * ntl + cx, 0, 4) + run(cy1 * ntl + cx, 0, 4);
+            if (nbx > 1) {
+                const int cx1 = (cx + 1) % ntl;
+                n_all += run(cy * ntl + cx1, 0, 4) + run(cy1 * ntl + cx1, 0, 4);
+            }
+            for (int s = 0; s < n_all; s += kF3Chunk)
+                fitems.push_back({cx, cy, nbx, s, std::min(kF3Chunk, n_all - s), 0, 0, 0});
+        }
+    }
     // longest items first so the tail of each launch is short
-    auto longer = [](const rn::TileItem& a, const rn::TileItem& b) { return a.count > b.count; };
-    std::stable_sort(items.begin(), items.end(), longer);
-    std::stable_sort(fitems.begin(), fitems.end(), longer);
+    std::stable_sort(items.begin(), items.end(),
+                     [](const rn::TileItem& a, const rn::TileItem& b) { return a.count > b.count; });
+    std::stable_sort(fitems.begin(), fitems.end(),
+                     [](const rn::F3Item& a, const rn::F3Item& b) { return a.count > b.count; });
     p.n_items = (int)items.size();
     p.n_fitems = (int)fitems.size();
     p.n_splits = (int)splits.size();

@@ -10,7 +10,7 @@ hipError_t launch_f1(const Plan& p, const float* img, hipStream_t st) {
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = fft_threads(L, 4);                                                  \
+        constexpr int NT = line_threads(L);                                                  \
         hipLaunchKernelGGL((k_f1_rows<L, NT>), grid, dim3(NT), 0, st, img, p.T1, p.psi_inv,     \
                            p.shift_n, p.tw_n);                                                 \
         break;                                                                                 \
@@ -28,7 +28,7 @@ hipError_t launch_f2(const Plan& p, hipStream_t st) {
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = fft_threads(L, 2);                                                  \
+        constexpr int NT = line_threads(L);                                                  \
         hipLaunchKernelGGL((k_f2_cols<L, NT>), grid, dim3(NT), 0, st, p.T1, p.grid, p.shift_n,  \
                            p.tw_n);                                                            \
         break;                                                                                 \
@@ -44,8 +44,8 @@ hipError_t launch_f2(const Plan& p, hipStream_t st) {
 template <int W, int T>
 static hipError_t launch_f3_wt(const Plan& p, hipStream_t st) {
     if (p.n_fitems == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_f3_tiles<W, T, 256>), dim3(p.n_fitems), dim3(256), 0, st, p.fitems, p.perm, p.grid,
-                       p.cs, p.kbc, p.kbS, p.Xr, p.G, p.n_det, p.n_views);
+    hipLaunchKernelGGL((k_f3_tiles<W, T, 512>), dim3(p.n_fitems), dim3(512), 0, st, p.fitems, p.offs4, p.perm,
+                       p.grid, p.cs, p.kbc, p.kbS, p.Xr, p.G, p.n_det, p.n_views);
     return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ struct Plan {
     float2* Xr = nullptr;        // n_views x (N/2+1) complex64 (forward polar samples)
     int* perm = nullptr;         // sorted sample ids
     int* offs4 = nullptr;        // 4 * n_bins + 1 class starts
-    TileItem* fitems = nullptr;
+    F3Item* fitems = nullptr;
     TileItem* items = nullptr;
     SplitTile* splits = nullptr;
     float2* partials = nullptr;

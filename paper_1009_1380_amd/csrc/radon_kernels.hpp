@@ -79,80 +79,126 @@ __device__ __forceinline__ int mod_pos(int a, int m) {
     return r < 0 ? r + m : r;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Renumber block b of nb so that each XCD gets a contiguous run of
+// logical blocks: neighbouring blocks, which share cache lines, then run
+// together on one XCD.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, k = b >> 3, per = nb >> 3, rem = nb & 7;
+    return x * per + min(x, rem) + k;
+}
+
 // ---------------------------------------------------------------- F1
-// Four image rows per workgroup (two packed pairs). Row i holds py = i - n/2,
-// column j holds px = j - n/2 (stored at px mod n in the length-n FFT).
-// Lines in LDS: [pair0 r=0, pair0 r=1, pair1 r=0, pair1 r=1].
+// Four image rows per workgroup, as two packed pairs done one after the other
+// (LDS holds one pair: lines r = 0 and r = 1). Row i holds py = i - n/2,
+// column j holds px = j - n/2 (stored at px mod n in the length-n FFT). The
+// four outputs of each frequency mx are kept in registers and written to
+// T1[mx][i0..i0+3] together (32 contiguous bytes).
 template <int NL, int NT>
 __global__ __launch_bounds__(NT) void k_f1_rows(const float* __restrict__ img, float2* __restrict__ T1,
                                                const float* __restrict__ psi_inv,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
-    __shared__ float2 lds[4 * NL];
+    constexpr int LS = lds_ls(NL);
+    constexpr int PM = (NL + 1 + NT - 1) / NT;   // frequencies mx per thread
+    __shared__ float2 lds[2 * LS];
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * 4;
-    for (int idx = tid; idx < 2 * NL; idx += NT) {
-        const int p = idx / NL;
-        const int j = idx - p * NL;
-        const int r0 = i0 + 2 * p;
-        const float pj = psi_inv[j];
-        float a = 0.f, b = 0.f;
-        if (r0 < NL) a = img[(size_t)r0 * NL + j] * psi_inv[r0] * pj;
-        if (r0 + 1 < NL) b = img[(size_t)(r0 + 1) * NL + j] * psi_inv[r0 + 1] * pj;
-        const int pos = (j + NL / 2) % NL;
-        const float2 z = make_float2(a, b);
-        lds[(2 * p) * NL + pos] = z;
-        lds[(2 * p + 1) * NL + pos] = cmul(z, shift[j]);
-    }
-    __syncthreads();
-    fft_lds<NL, 4, NT>(lds, tw, tid);
-    for (int m = tid; m <= NL; m += NT) {
-        float2 out[4];
+    const int i0 = 4 * xcd_block(blockIdx.x, gridDim.x);
+    float2 out[PM][4];
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            float2 zk, zc;
-            if ((m & 1) == 0) {
-                const int k = m >> 1;
-                zk = lds[(2 * p) * NL + k];
-                zc = cconj(lds[(2 * p) * NL + (NL - k) % NL]);
-            } else {
-                const int k = m >> 1;
-                zk = lds[(2 * p + 1) * NL + k];
-                zc = cconj(lds[(2 * p + 1) * NL + NL - 1 - k]);
-            }
-            const float2 sm = cadd(zk, zc), df = csub(zk, zc);
-            out[2 * p] = make_float2(0.5f * sm.x, 0.5f * sm.y);
-            out[2 * p + 1] = make_float2(0.5f * df.y, -0.5f * df.x);   // (zk - zc) / 2i
+    for (int p = 0; p < 2; ++p) {
+        const int r0 = i0 + 2 * p;
+        for (int j = tid; j < NL; j += NT) {
+            const float pj = psi_inv[j];
+            float a = 0.f, b = 0.f;
+            if (r0 < NL) a = img[(size_t)r0 * NL + j] * psi_inv[r0] * pj;
+            if (r0 + 1 < NL) b = img[(size_t)(r0 + 1) * NL + j] * psi_inv[r0 + 1] * pj;
+            const int pos = lds_pad((j + NL / 2) % NL);
+            const float2 z = make_float2(a, b);
+            lds[pos] = z;
+            lds[LS + pos] = cmul(z, shift[j]);
         }
-        float2* dst = T1 + (size_t)m * NL + i0;
-        if (i0 + 1 < NL) *reinterpret_cast<float4*>(dst) = make_float4(out[0].x, out[0].y, out[1].x, out[1].y);
-        if (i0 + 3 < NL) *reinterpret_cast<float4*>(dst + 2) = make_float4(out[2].x, out[2].y, out[3].x, out[3].y);
+        __syncthreads();
+        fft_lds<NL, 2, NT>(lds, tw, tid);
+#pragma unroll
+        for (int c = 0; c < PM; ++c) {
+            const int m = tid + c * NT;
+            if (m <= NL) {
+                float2 zk, zc;
+                if ((m & 1) == 0) {
+                    const int k = m >> 1;
+                    zk = lds[lds_pad(k)];
+                    zc = cconj(lds[lds_pad((NL - k) % NL)]);
+                } else {
+                    const int k = m >> 1;
+                    zk = lds[LS + lds_pad(k)];
+                    zc = cconj(lds[LS + lds_pad(NL - 1 - k)]);
+                }
+                const float2 sm = cadd(zk, zc), df = csub(zk, zc);
+                out[c][2 * p] = make_float2(0.5f * sm.x, 0.5f * sm.y);
+                out[c][2 * p + 1] = make_float2(0.5f * df.y, -0.5f * df.x);   // (zk - zc) / 2i
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < PM; ++c) {
+        const int m = tid + c * NT;
+        if (m <= NL) {
+            float2* dst = T1 + (size_t)m * NL + i0;
+            if (i0 + 1 < NL)
+                *reinterpret_cast<float4*>(dst) = make_float4(out[c][0].x, out[c][0].y, out[c][1].x, out[c][1].y);
+            if (i0 + 3 < NL)
+                *reinterpret_cast<float4*>(dst + 2) = make_float4(out[c][2].x, out[c][2].y, out[c][3].x, out[c][3].y);
+        }
     }
 }
 
 // ---------------------------------------------------------------- F2
 // One half-plane line mx per workgroup: FFT along py of T1[mx][.] into
-// grid[mx][my], my = 2k + r from two length-n transforms.
+// grid[mx][my], my = 2k + r from two length-n transforms done one after the
+// other in one LDS line (the input and the r = 0 result wait in registers).
 template <int NL, int NT>
 __global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, float2* __restrict__ grid,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
-    __shared__ float2 lds[2 * NL];
+    constexpr int PE = (NL + NT - 1) / NT;
+    __shared__ float2 lds[lds_ls(NL)];
     const int tid = threadIdx.x;
     const int mx = blockIdx.x;
     const float2* src = T1 + (size_t)mx * NL;
-    for (int i = tid; i < NL; i += NT) {
-        const float2 c = src[i];
-        const int pos = (i + NL / 2) % NL;
-        lds[pos] = c;
-        lds[NL + pos] = cmul(c, shift[i]);
+    float2 c[PE], z0[PE];
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const int i = tid + e * NT;
+        if (i < NL) {
+            c[e] = src[i];
+            lds[lds_pad((i + NL / 2) % NL)] = c[e];
+        }
     }
     __syncthreads();
-    fft_lds<NL, 2, NT>(lds, tw, tid);
+    fft_lds<NL, 1, NT>(lds, tw, tid);
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const int k = tid + e * NT;
+        if (k < NL) z0[e] = lds[lds_pad(k)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const int i = tid + e * NT;
+        if (i < NL) lds[lds_pad((i + NL / 2) % NL)] = cmul(c[e], shift[i]);
+    }
+    __syncthreads();
+    fft_lds<NL, 1, NT>(lds, tw, tid);
     float4* dst = reinterpret_cast<float4*>(grid + (size_t)mx * (2 * NL));
-    for (int k = tid; k < NL; k += NT) {
-        const float2 e = lds[k], o = lds[NL + k];
-        dst[k] = make_float4(e.x, e.y, o.x, o.y);
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const int k = tid + e * NT;
+        if (k < NL) {
+            const float2 o = lds[lds_pad(k)];
+            dst[k] = make_float4(z0[e].x, z0[e].y, o.x, o.y);
+        }
     }
 }
 
@@ -188,27 +234,46 @@ struct TileItem {
 };
 
 // ---------------------------------------------------------------- F3
-// Kaiser-Bessel interpolation of the polar samples from the half-plane grid,
-// one tile per workgroup. The tile and its (W-1) halo are staged in LDS
-// (points with mx < 0 read as conjugates of their mirror, wrap mod G), then
-// every sample whose footprint origin is in the tile is interpolated from LDS.
-// Of each conjugate pair (q, -q) exactly one member is evaluated: q >= 0 when
-// its origin tile is a forward column, else -q (result conjugated); the pair
-// (-N/2, +N/2) likewise. Results go to Xr[a][t], t = |q| (t = N/2: Nyquist).
+// Kaiser-Bessel interpolation of the polar samples from the half-plane grid.
+// One workgroup per super-tile of 2 x 2 bins (the bins of tile columns cx and
+// cx+1 mod ntl, rows cy and cy+1). The super-tile and its (W-1) halo are
+// staged in LDS (points with mx < 0 read as conjugates of their mirror, wrap
+// mod G), then every sample whose footprint origin is in one of the four bins
+// is interpolated from LDS. Of each conjugate pair (q, -q) exactly one member
+// is evaluated: q >= 0 when its origin tile is a forward column, else -q
+// (result conjugated); the pair (-N/2, +N/2) likewise. Results go to
+// Xr[a][t], t = |q| (t = N/2: Nyquist).
+struct F3Item {
+    int cx, cy;      // first bin of the super-tile, centred tile coordinates
+    int nbx;         // bins of the super-tile along u that are forward columns (1 or 2)
+    int start;       // first sample of the slice within the concatenated bins
+    int count;       // samples in this slice
+    int pad0, pad1, pad2;
+};
+
 template <int W, int T, int NT>
-__global__ __launch_bounds__(NT) void k_f3_tiles(const TileItem* __restrict__ items, const int* __restrict__ perm,
-                                                const float2* __restrict__ grid, const double2* __restrict__ cs,
-                                                const float4* __restrict__ kbc, float kbS,
-                                                float2* __restrict__ Xr, int G, int ND, int n_views) {
-    constexpr int P = T + W - 1;
+__global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ items, const int* __restrict__ offs4,
+                                                const int* __restrict__ perm, const float2* __restrict__ grid,
+                                                const double2* __restrict__ cs, const float4* __restrict__ kbc,
+                                                float kbS, float2* __restrict__ Xr, int G, int ND, int n_views) {
+    constexpr int P = 2 * T + W - 1;
     __shared__ float2 tile[P * P];   // [lx][ly], lx along u (mx), ly along v (my)
     const int tid = threadIdx.x;
-    const TileItem it = items[blockIdx.x];
+    const F3Item it = items[blockIdx.x];
     const int x0 = it.cx * T, y0 = it.cy * T;
     const int ntl = G / T;
     const int M = n_views * ND;
     const int HQ = ND / 2 + 1;
     const float hw = 0.5f * (float)W;
+    // sample ranges of the (up to) four bins, in the order (x0,y0) (x1,y0) (x0,y1) (x1,y1)
+    const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
+    const int b0 = it.cy * ntl + it.cx, b1 = it.cy * ntl + cx1, b2 = cy1 * ntl + it.cx, b3 = cy1 * ntl + cx1;
+    const int s0 = offs4[4 * b0], n0 = offs4[4 * b0 + 4] - s0;
+    const int s1 = offs4[4 * b1], n1 = (it.nbx > 1) ? offs4[4 * b1 + 4] - s1 : 0;
+    const int s2 = offs4[4 * b2], n2 = offs4[4 * b2 + 4] - s2;
+    const int s3 = offs4[4 * b3];
+
+    // stage the super-tile
     for (int e = tid; e < P * P; e += NT) {
         const int lx = e / P, ly = e - lx * P;
         int mx = mod_pos(x0 + lx, G) - G / 2;        // in [-G/2, G/2)
@@ -224,7 +289,12 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const TileItem* __restrict__ it
     }
     __syncthreads();
     for (int k = tid; k < it.count; k += NT) {
-        const int v = perm[it.start + k];
+        int u = it.start + k, pos;
+        if (u < n0) pos = s0 + u;
+        else if ((u -= n0) < n1) pos = s1 + u;
+        else if ((u -= n1) < n2) pos = s2 + u;
+        else pos = s3 + (u - n2);
+        const int v = perm[pos];
         int a, q;
         decode_sample(v, M, ND, a, q);
         const double2 csa = cs[a];
@@ -242,8 +312,8 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const TileItem* __restrict__ it
             conj_out = true;
         }
         const SampleGeom g = sample_geom(csa.x, csa.y, q, G, ND);
-        const int ox = footprint_origin(g.bu, W, G) - x0;
-        const int oy = footprint_origin(g.bv, W, G) - y0;
+        const int ox = mod_pos(footprint_origin(g.bu, W, G) - x0, G);   // in [0, 2T)
+        const int oy = mod_pos(footprint_origin(g.bv, W, G) - y0, G);
         float wy[W];
 #pragma unroll
         for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbc, kbS, hw);
@@ -274,7 +344,7 @@ template <int ND, int NT>
 __global__ __launch_bounds__(NT) void k_f4_rays(const float2* __restrict__ Xr, float* __restrict__ sino,
                                                const float2* __restrict__ tw, int n_views) {
     constexpr int HQ = ND / 2 + 1;
-    __shared__ float2 lds[ND];
+    __shared__ float2 lds[lds_ls(ND)];
     const int tid = threadIdx.x;
     const int a0 = blockIdx.x * 2;
     const bool has_b = a0 + 1 < n_views;
@@ -294,13 +364,13 @@ __global__ __launch_bounds__(NT) void k_f4_rays(const float2* __restrict__ Xr, f
             A = cconj(xa[ND - q]);
             B = has_b ? cconj(xb[ND - q]) : zero;
         }
-        lds[q] = make_float2(A.x - B.y, -(A.y + B.x));
+        lds[lds_pad(q)] = make_float2(A.x - B.y, -(A.y + B.x));
     }
     __syncthreads();
     fft_lds<ND, 1, NT>(lds, tw, tid);
     const float inv = 1.0f / (float)ND;
     for (int d = tid; d < ND; d += NT) {
-        const float2 z = cconj(lds[(d + ND / 2) % ND]);
+        const float2 z = cconj(lds[lds_pad((d + ND / 2) % ND)]);
         sino[(size_t)a0 * ND + d] = z.x * inv;
         if (has_b) sino[(size_t)(a0 + 1) * ND + d] = z.y * inv;
     }
@@ -314,20 +384,20 @@ template <int ND, int NT>
 __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, float2* __restrict__ Yh,
                                                const float2* __restrict__ tw, int n_views) {
     constexpr int HQ = ND / 2 + 1;
-    __shared__ float2 lds[ND];
+    __shared__ float2 lds[lds_ls(ND)];
     const int tid = threadIdx.x;
     const int a0 = blockIdx.x * 2;
     for (int d = tid; d < ND; d += NT) {
         const float ya = (a0 < n_views) ? sino[(size_t)a0 * ND + d] : 0.f;
         const float yb = (a0 + 1 < n_views) ? sino[(size_t)(a0 + 1) * ND + d] : 0.f;
-        lds[(d + ND / 2) % ND] = make_float2(ya, yb);
+        lds[lds_pad((d + ND / 2) % ND)] = make_float2(ya, yb);
     }
     __syncthreads();
     fft_lds<ND, 1, NT>(lds, tw, tid);
     const float sc = 0.5f / (float)ND;
     for (int q = tid; q < HQ; q += NT) {
-        const float2 zq = lds[q];
-        const float2 zc = cconj(lds[(ND - q) % ND]);
+        const float2 zq = lds[lds_pad(q)];
+        const float2 zc = cconj(lds[lds_pad((ND - q) % ND)]);
         const float2 sm = cadd(zq, zc), df = csub(zq, zc);
         const float h = (q == ND / 2) ? 0.5f * sc : sc;
         if (a0 < n_views) Yh[(size_t)a0 * HQ + q] = make_float2(h * sm.x, h * sm.y);
@@ -336,40 +406,44 @@ __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, 
 }
 
 // ---------------------------------------------------------------- A2
-// Deterministic binned spreading, one wave per work item (a slice of one
-// output tile's visit list). The visit list of tile (cx, cy) is the
-// concatenation of: the diagonal neighbour bin's class 2, the v-neighbour
-// bin's classes 2-3, the u-neighbour bin's classes 1-2 and the own bin (all
-// classes) -- exactly the samples whose footprint reaches the tile.
+// Deterministic binned spreading. One workgroup per work item: a slice of
+// at most A2_MAX_VISITS visits of one output tile's visit list, which is the
+// concatenation of the diagonal neighbour bin's class 2, the v-neighbour's
+// classes 2-3, the u-neighbour's classes 1-2 and the whole own bin -- exactly
+// the samples whose footprint reaches the tile.
 //
-// Lane l takes visits l*S .. l*S+S-1 (S = ceil(count/64)), one per round. In
-// a round each lane computes its sample's W x-weights and W values Y*wy, then
-// adds its W x W footprint into a halo'd LDS accumulator, one footprint point
-// per instruction. Lanes whose footprint origins coincide would collide, so
-// a round runs in sub-rounds: the lowest pending lane of each origin cell
-// (claimed with an integer atomic min, deterministic) adds, the others wait.
-// Every grid value is therefore accumulated in one fixed order.
+// Every thread prepares up to A2_VPT visits (W x-weights, W values Y*wy).
+// Contributions are accumulated as 64-bit fixed-point integers in a halo'd
+// LDS tile with integer atomic adds: integer addition is exact and
+// commutative, so the sums do not depend on the order in which lanes and
+// waves arrive, and the result is bitwise reproducible without any floating-
+// point atomics. Each contribution is the exact product of x = round(wx*2^24)
+// (wx in [0, 1]) and y = round(Y*wy*2^s) (|y| < 2^31); s is chosen per work
+// item from the item's largest |Y*wy| so that count * 2^24 * max|y| < 2^62,
+// which bounds every partial sum. The relative rounding of y (2^-28 or finer
+// of the item's largest value) is far below float32 resolution of the sums.
+constexpr int A2_NT = 256;
+constexpr int A2_VPT = 4;
+constexpr int A2_MAX_VISITS = A2_NT * A2_VPT;
+
 template <int W, int T>
-__global__ __launch_bounds__(64) void k_a2_spread(const TileItem* __restrict__ items,
-                                                 const int* __restrict__ offs4, const int* __restrict__ perm,
-                                                 const float2* __restrict__ Yh, const double2* __restrict__ cs,
-                                                 const float4* __restrict__ kbc, float kbS,
-                                                 float2* __restrict__ grid, float2* __restrict__ partials,
-                                                 int G, int ND, int n_views) {
+__global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict__ items,
+                                                    const int* __restrict__ offs4, const int* __restrict__ perm,
+                                                    const float2* __restrict__ Yh, const double2* __restrict__ cs,
+                                                    const float4* __restrict__ kbc, float kbS,
+                                                    float2* __restrict__ grid, float2* __restrict__ partials,
+                                                    int G, int ND, int n_views) {
     constexpr int P = T + 2 * (W - 1);   // accumulator side: local [-(W-1), T+W-1)
-    constexpr int C = T + W - 1;         // origin cells: local [-(W-1), T)
-    constexpr int FREE = 64;
-    __shared__ float2 acc[P * P];
-    __shared__ int owner[C * C];
-    const int lane = threadIdx.x;
+    __shared__ unsigned long long acc[2 * P * P];   // (re, im) per point
+    __shared__ float wmax[A2_NT / 64];
+    const int tid = threadIdx.x;
     const TileItem it = items[blockIdx.x];
     const int ntl = G / T;
     const int M = n_views * ND;
     const int HQ = ND / 2 + 1;
     const float hw = 0.5f * (float)W;
 
-    for (int e = lane; e < P * P; e += 64) acc[e] = make_float2(0.f, 0.f);
-    for (int e = lane; e < C * C; e += 64) owner[e] = FREE;
+    for (int e = tid; e < 2 * P * P; e += A2_NT) acc[e] = 0ull;
 
     const int xl = (it.cx + ntl - 1) % ntl, yu = (it.cy + ntl - 1) % ntl;
     const int b_ul = yu * ntl + xl, b_u = yu * ntl + it.cx, b_l = it.cy * ntl + xl, b_o = it.cy * ntl + it.cx;
@@ -378,17 +452,16 @@ __global__ __launch_bounds__(64) void k_a2_spread(const TileItem* __restrict__ i
     const int s2 = offs4[4 * b_l + 1], n2 = offs4[4 * b_l + 3] - s2;
     const int s3 = offs4[4 * b_o];
     const int x0 = it.cx * T, y0 = it.cy * T;
-    const int xvalid = (it.cx == 0) ? 1 : T;   // tile column 0 holds only mx = G/2
-    const int S = (it.count + 63) / 64;
-    __syncthreads();
 
-    for (int r = 0; r < S; ++r) {
-        const int t = lane * S + r;
-        bool pending = t < it.count;
-        int base = 0, cell = 0;
-        float wx[W];
-        float2 ywy[W];
-        if (pending) {
+    int base[A2_VPT];
+    float wx[A2_VPT][W];
+    float2 ywy[A2_VPT][W];
+    float mx_abs = 0.f;
+#pragma unroll
+    for (int k = 0; k < A2_VPT; ++k) {
+        const int t = tid + k * A2_NT;
+        base[k] = -1;
+        if (t < it.count) {
             int u = it.start + t, pos;
             if (u < n0) pos = s0 + u;
             else if ((u -= n0) < n1) pos = s1 + u;
@@ -409,57 +482,65 @@ __global__ __launch_bounds__(64) void k_a2_spread(const TileItem* __restrict__ i
             if (ox < -G / 2) ox += G;
             if (oy >= G / 2) oy -= G;
             if (oy < -G / 2) oy += G;
-            base = (ox + W - 1) * P + (oy + W - 1);
-            cell = (ox + W - 1) * C + (oy + W - 1);
+            base[k] = (ox + W - 1) * P + (oy + W - 1);
 #pragma unroll
-            for (int al = 0; al < W; ++al) wx[al] = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbc, kbS, hw);
+            for (int al = 0; al < W; ++al)
+                wx[k][al] = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbc, kbS, hw);
 #pragma unroll
             for (int gm = 0; gm < W; ++gm) {
                 const float wy = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbc, kbS, hw);
-                ywy[gm] = make_float2(Y.x * wy, Y.y * wy);
+                ywy[k][gm] = make_float2(Y.x * wy, Y.y * wy);
+                mx_abs = fmaxf(mx_abs, fmaxf(fabsf(ywy[k][gm].x), fabsf(ywy[k][gm].y)));
             }
         }
-        while (__ballot(pending) != 0) {
-            if (pending) atomicMin(&owner[cell], lane);
-            __builtin_amdgcn_wave_barrier();
-            const bool win = pending && __hip_atomic_load(&owner[cell], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_WORKGROUP) == lane;
-            if (win) {
-                // One footprint point per step. Winners have distinct origin
-                // cells, so within a step every lane touches its own address,
-                // but step k of one lane may hit the address of step j of
-                // another: the compiler barrier keeps each step's read after
-                // the previous step's write (the LDS executes a wave's
-                // instructions in order).
-                float2* dst = acc + base;
+    }
+    // item-wide max |Y*wy| (order-independent)
 #pragma unroll
-                for (int al = 0; al < W; ++al) {
+    for (int off = 32; off >= 1; off >>= 1) mx_abs = fmaxf(mx_abs, __shfl_xor(mx_abs, off));
+    if ((tid & 63) == 0) wmax[tid >> 6] = mx_abs;
+    __syncthreads();
+    float m = wmax[0];
 #pragma unroll
-                    for (int gm = 0; gm < W; ++gm) {
-                        float2 o = dst[al * P + gm];
-                        o.x = fmaf(wx[al], ywy[gm].x, o.x);
-                        o.y = fmaf(wx[al], ywy[gm].y, o.y);
-                        dst[al * P + gm] = o;
-                        asm volatile("" ::: "memory");
-                    }
-                }
-                __hip_atomic_store(&owner[cell], FREE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (int w = 1; w < A2_NT / 64; ++w) m = fmaxf(m, wmax[w]);
+    // scale 2^s: max|y| < 2^31 and count * 2^24 * 2^s * max < 2^62
+    int e = 0;
+    (void)frexpf(m, &e);                       // m < 2^e
+    int lc = 0;
+    while ((1 << lc) < it.count) ++lc;         // count <= 2^lc
+    const int s = min(31, 38 - lc) - e;
+#pragma unroll
+    for (int k = 0; k < A2_VPT; ++k) {
+        if (base[k] < 0) continue;
+        int xi[W];
+#pragma unroll
+        for (int al = 0; al < W; ++al) xi[al] = __float2int_rn(wx[k][al] * 16777216.0f);
+#pragma unroll
+        for (int gm = 0; gm < W; ++gm) {
+            const long long yr = __float2int_rn(ldexpf(ywy[k][gm].x, s));
+            const long long yi = __float2int_rn(ldexpf(ywy[k][gm].y, s));
+#pragma unroll
+            for (int al = 0; al < W; ++al) {
+                const int idx = 2 * (base[k] + al * P + gm);
+                atomicAdd(&acc[idx], (unsigned long long)(yr * xi[al]));
+                atomicAdd(&acc[idx + 1], (unsigned long long)(yi * xi[al]));
             }
-            pending = pending && !win;
-            __builtin_amdgcn_wave_barrier();
         }
     }
     __syncthreads();
     // write out: local (lx, ly) -> mx = (x0 + lx - G/2) mod G, my = (y0 + ly - G/2) mod G
+    const int xvalid = (it.cx == 0) ? 1 : T;   // tile column 0 holds only mx = G/2
     const int my0 = mod_pos(y0 - G / 2, G);
-    for (int e = lane; e < xvalid * T; e += 64) {
-        const int lx = e / T, ly = e - lx * T;
-        const float2 val = acc[(lx + W - 1) * P + (ly + W - 1)];
+    const int sh = -(s + 24);
+    for (int e2 = tid; e2 < xvalid * T; e2 += A2_NT) {
+        const int lx = e2 / T, ly = e2 - lx * T;
+        const int idx = 2 * ((lx + W - 1) * P + (ly + W - 1));
+        const float2 val = make_float2((float)ldexp((double)(long long)acc[idx], sh),
+                                       (float)ldexp((double)(long long)acc[idx + 1], sh));
         if (it.slot < 0) {
             const int mx = mod_pos(x0 + lx - G / 2, G);
             grid[(size_t)mx * G + my0 + ly] = val;
         } else {
-            partials[(size_t)it.slot * T * T + e] = val;
+            partials[(size_t)it.slot * T * T + e2] = val;
         }
     }
 }
@@ -489,84 +570,119 @@ __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__
 
 // ---------------------------------------------------------------- A3
 // One grid line mx per workgroup: h[p] = sum_my H[my] e^{+2 pi i my p/G} for
-// the n rows p = -n/2..n/2-1 = IFFT_n(H_even)[p] + e^{i pi p/n} IFFT_n(H_odd)[p].
+// the n rows p = -n/2..n/2-1 = IFFT_n(H_even)[p] + e^{i pi p/n} IFFT_n(H_odd)[p];
+// the two inverse transforms share one LDS line, one after the other.
 template <int NL, int NT>
 __global__ __launch_bounds__(NT) void k_a3_cols(const float2* __restrict__ grid, float2* __restrict__ T1,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
-    __shared__ float2 lds[2 * NL];
+    constexpr int PE = (NL + NT - 1) / NT;
+    __shared__ float2 lds[lds_ls(NL)];
     const int tid = threadIdx.x;
     const int mx = blockIdx.x;
     const float4* src = reinterpret_cast<const float4*>(grid + (size_t)mx * (2 * NL));
-    for (int k = tid; k < NL; k += NT) {
-        const float4 v = src[k];
-        lds[k] = make_float2(v.x, -v.y);        // conj for the inverse
-        lds[NL + k] = make_float2(v.z, -v.w);
+    float2 odd[PE], ev[PE];
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const int k = tid + e * NT;
+        if (k < NL) {
+            const float4 v = src[k];
+            lds[lds_pad(k)] = make_float2(v.x, -v.y);        // conj for the inverse
+            odd[e] = make_float2(v.z, -v.w);
+        }
     }
     __syncthreads();
-    fft_lds<NL, 2, NT>(lds, tw, tid);
+    fft_lds<NL, 1, NT>(lds, tw, tid);
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const int i = tid + e * NT;
+        if (i < NL) ev[e] = cconj(lds[lds_pad((i + NL / 2) % NL)]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const int k = tid + e * NT;
+        if (k < NL) lds[lds_pad(k)] = odd[e];
+    }
+    __syncthreads();
+    fft_lds<NL, 1, NT>(lds, tw, tid);
     float2* dst = T1 + (size_t)mx * NL;
-    for (int i = tid; i < NL; i += NT) {
-        const int idx = (i + NL / 2) % NL;
-        const float2 e = cconj(lds[idx]), o = cconj(lds[NL + idx]);
-        dst[i] = cadd(e, cmul(cconj(shift[i]), o));
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const int i = tid + e * NT;
+        if (i < NL) {
+            const float2 o = cconj(lds[lds_pad((i + NL / 2) % NL)]);
+            dst[i] = cadd(ev[e], cmul(cconj(shift[i]), o));
+        }
     }
 }
 
 // ---------------------------------------------------------------- A4
-// Four image rows per workgroup (two packed pairs): complex-to-real inverse
-// FFT along mx of T1[mx][i], mx = 0..n (Hermitian extension to G points),
-// keep px = -n/2..n/2-1, deapodize.
+// Four image rows per workgroup (two packed pairs, one after the other):
+// complex-to-real inverse FFT along mx of T1[mx][i], mx = 0..n (Hermitian
+// extension to G points), keep px = -n/2..n/2-1, deapodize. The four inputs
+// of each mx are read together (32 contiguous bytes) and wait in registers.
 template <int NL, int NT>
 __global__ __launch_bounds__(NT) void k_a4_rows(const float2* __restrict__ T1, float* __restrict__ img,
                                                const float* __restrict__ psi_inv,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
-    __shared__ float2 lds[4 * NL];
+    constexpr int LS = lds_ls(NL);
+    constexpr int PM = (NL + 1 + NT - 1) / NT;
+    __shared__ float2 lds[2 * LS];
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * 4;
-    for (int m = tid; m <= NL; m += NT) {
-        const float2* src = T1 + (size_t)m * NL + i0;
-        float2 X[4];
-        const float4 v01 = *reinterpret_cast<const float4*>(src);
-        X[0] = make_float2(v01.x, v01.y);
-        X[1] = make_float2(v01.z, v01.w);
-        if (i0 + 3 < NL) {
-            const float4 v23 = *reinterpret_cast<const float4*>(src + 2);
-            X[2] = make_float2(v23.x, v23.y);
-            X[3] = make_float2(v23.z, v23.w);
-        } else {
-            X[2] = X[3] = make_float2(0.f, 0.f);
-        }
+    const int i0 = 4 * xcd_block(blockIdx.x, gridDim.x);
+    float2 X[PM][4];
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            float2 X1 = X[2 * p], X2 = X[2 * p + 1];
-            if (m == 0 || m == NL) { X1.y = 0.f; X2.y = 0.f; }
-            const float2 z = make_float2(X1.x - X2.y, X1.y + X2.x);          // X1 + i X2
-            float2* even = lds + (2 * p) * NL;
-            float2* odd = lds + (2 * p + 1) * NL;
-            // position m, stored conjugated for the inverse
-            if ((m & 1) == 0) even[m >> 1] = cconj(z); else odd[m >> 1] = cconj(z);
-            if (m >= 1 && m <= NL - 1) {
-                const int mm = 2 * NL - m;
-                const float2 zm = make_float2(X1.x + X2.y, -X1.y + X2.x);    // conj X1 + i conj X2
-                if ((mm & 1) == 0) even[mm >> 1] = cconj(zm); else odd[mm >> 1] = cconj(zm);
+    for (int c = 0; c < PM; ++c) {
+        const int m = tid + c * NT;
+        if (m <= NL) {
+            const float2* src = T1 + (size_t)m * NL + i0;
+            const float4 v01 = *reinterpret_cast<const float4*>(src);
+            X[c][0] = make_float2(v01.x, v01.y);
+            X[c][1] = make_float2(v01.z, v01.w);
+            if (i0 + 3 < NL) {
+                const float4 v23 = *reinterpret_cast<const float4*>(src + 2);
+                X[c][2] = make_float2(v23.x, v23.y);
+                X[c][3] = make_float2(v23.z, v23.w);
+            } else {
+                X[c][2] = X[c][3] = make_float2(0.f, 0.f);
             }
         }
     }
-    __syncthreads();
-    fft_lds<NL, 4, NT>(lds, tw, tid);
-    for (int idx = tid; idx < 2 * NL; idx += NT) {
-        const int p = idx / NL;
-        const int j = idx - p * NL;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        float2* even = lds;
+        float2* odd = lds + LS;
+#pragma unroll
+        for (int c = 0; c < PM; ++c) {
+            const int m = tid + c * NT;
+            if (m <= NL) {
+                float2 X1 = X[c][2 * p], X2 = X[c][2 * p + 1];
+                if (m == 0 || m == NL) { X1.y = 0.f; X2.y = 0.f; }
+                const float2 z = make_float2(X1.x - X2.y, X1.y + X2.x);          // X1 + i X2
+                // position m, stored conjugated for the inverse
+                if ((m & 1) == 0) even[lds_pad(m >> 1)] = cconj(z); else odd[lds_pad(m >> 1)] = cconj(z);
+                if (m >= 1 && m <= NL - 1) {
+                    const int mm = 2 * NL - m;
+                    const float2 zm = make_float2(X1.x + X2.y, -X1.y + X2.x);    // conj X1 + i conj X2
+                    if ((mm & 1) == 0) even[lds_pad(mm >> 1)] = cconj(zm); else odd[lds_pad(mm >> 1)] = cconj(zm);
+                }
+            }
+        }
+        __syncthreads();
+        fft_lds<NL, 2, NT>(lds, tw, tid);
         const int r0 = i0 + 2 * p;
-        const int pos = (j + NL / 2) % NL;
-        const float2 e = cconj(lds[(2 * p) * NL + pos]);
-        const float2 o = cconj(lds[(2 * p + 1) * NL + pos]);
-        const float2 z = cadd(e, cmul(cconj(shift[j]), o));
-        const float pj = psi_inv[j];
-        if (r0 < NL) img[(size_t)r0 * NL + j] = z.x * psi_inv[r0] * pj;
-        if (r0 + 1 < NL) img[(size_t)(r0 + 1) * NL + j] = z.y * psi_inv[r0 + 1] * pj;
+        for (int j = tid; j < NL; j += NT) {
+            const int pos = lds_pad((j + NL / 2) % NL);
+            const float2 e = cconj(lds[pos]);
+            const float2 o = cconj(lds[LS + pos]);
+            const float2 z = cadd(e, cmul(cconj(shift[j]), o));
+            const float pj = psi_inv[j];
+            if (r0 < NL) img[(size_t)r0 * NL + j] = z.x * psi_inv[r0] * pj;
+            if (r0 + 1 < NL) img[(size_t)(r0 + 1) * NL + j] = z.y * psi_inv[r0 + 1] * pj;
+        }
+        __syncthreads();
     }
 }
 
@@ -574,17 +690,17 @@ __global__ __launch_bounds__(NT) void k_a4_rows(const float2* __restrict__ T1, f
 template <int LEN, int NT>
 __global__ __launch_bounds__(NT) void k_fft_test(const float2* __restrict__ in, float2* __restrict__ out,
                                                 const float2* __restrict__ tw, int inverse) {
-    __shared__ float2 lds[LEN];
+    __shared__ float2 lds[lds_ls(LEN)];
     const int tid = threadIdx.x;
     const size_t base = (size_t)blockIdx.x * LEN;
     for (int i = tid; i < LEN; i += NT) {
         float2 v = in[base + i];
-        lds[i] = inverse ? cconj(v) : v;
+        lds[lds_pad(i)] = inverse ? cconj(v) : v;
     }
     __syncthreads();
     fft_lds<LEN, 1, NT>(lds, tw, tid);
     for (int i = tid; i < LEN; i += NT) {
-        float2 v = lds[i];
+        float2 v = lds[lds_pad(i)];
         out[base + i] = inverse ? cconj(v) : v;
     }
 }

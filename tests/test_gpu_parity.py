@@ -281,3 +281,62 @@ def test_stream_and_profiling():
     assert all(ms >= 0 for ms, _ in times.values())
     plan.set_profiling(False)
     assert torch.isfinite(a).all()
+
+
+# ------------------------------------------------------------------ full size
+
+def test_full_size_slice_vs_oracle():
+    """Full-size slice (the benchmark's launch configuration): 2560^2 disk
+    phantom with noise, 1024 views x 2560 bins; forward and adjoint of the
+    whole arrays against O-grid (FP64)."""
+    from radon_inputs import config2_phantom
+    note("full size: phantom + plan")
+    n, nv = 2560, 1024
+    x = config2_phantom(0, n)
+    ang = uniform_angles(nv)
+    plan = Plan(n, ang, n)
+    yd = plan.forward(to_dev(x))
+    ad = plan.adjoint(yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    a = ad.cpu().numpy()
+    note("full size: oracle forward")
+    y_ref = grid_forward(x.astype(np.float64), ang, n)
+    ey = rel(y, y_ref)
+    note(f"full size forward rel L2 {ey:.3e}")
+    assert ey < TOL_GRID
+    note("full size: oracle adjoint")
+    a_ref = grid_adjoint(y.astype(np.float64), ang, n)
+    ea = rel(a, a_ref)
+    note(f"full size adjoint rel L2 {ea:.3e}")
+    assert ea < TOL_GRID
+
+
+def test_full_size_gaussian_closed_form():
+    """G5 at full size: no O(n^2 M) work, closed-form projections."""
+    note("full size gaussian")
+    n, nv = 2560, 64
+    cx, cy, sg = 311.7, -402.2, 4.0
+    x = gaussian_blob(n, cx, cy, sg).astype(np.float32)
+    ang = uniform_angles(nv)
+    y = Plan(n, ang, n).forward(to_dev(x)).cpu().numpy()
+    s = np.arange(n) - n / 2
+    ref = np.stack([np.sqrt(2 * np.pi) * sg * np.exp(-(s - (cx * np.cos(t) + cy * np.sin(t))) ** 2 / (2 * sg * sg))
+                    for t in ang])
+    assert rel(y, ref) < TOL_EXACT
+
+
+def test_full_size_adjoint_identity_and_determinism():
+    note("full size adjoint identity")
+    n, nv = 2560, 1024
+    plan = Plan(n, uniform_angles(nv), n)
+    x = to_dev(random_image(61, n))
+    y = to_dev(random_sinogram(62, nv, n))
+    Ax = plan.forward(x)
+    Aty = plan.adjoint(y)
+    Ax2 = plan.forward(x)
+    Aty2 = plan.adjoint(y)
+    assert torch.equal(Ax, Ax2) and torch.equal(Aty, Aty2)
+    lhs = float(torch.sum(Ax.double() * y.double()))
+    rhs = float(torch.sum(x.double() * Aty.double()))
+    assert abs(lhs - rhs) <= 1e-5 * float(torch.linalg.norm(Ax.double())) * float(torch.linalg.norm(y.double()))
