@@ -84,6 +84,17 @@ radon_status_t radon_forward(radon_plan_t plan, const float* img_dev, float* sin
 radon_status_t radon_adjoint(radon_plan_t plan, const float* sino_dev, float* img_dev,
                              void* stream);
 
+/*
+ * Filtered adjoint (filtered back-projection through the Fourier slice
+ * theorem): the adjoint with every ray spectrum weighted by the ramp
+ * w_q = (pi/n_views) H(q), H the DFT of the band-limited spatial ramp kernel
+ * h[0] = 1/4, h[k] = -1/(pi k)^2 for odd k, 0 for even k != 0, |k| < N/2.
+ * For views uniform in [0, pi) it approximately inverts radon_forward inside
+ * the inscribed circle. Read here as the "standard tomographic processing"
+ * of the paper's introduction. sino_dev (n_views*n_det) -> img_dev (n*n).
+ */
+radon_status_t radon_fbp(radon_plan_t plan, const float* sino_dev, float* img_dev, void* stream);
+
 /* batch slices that share the plan's geometry, back to back on the stream:
  * imgs_dev is batch*n*n float32, sinos_dev is batch*n_views*n_det float32. */
 radon_status_t radon_forward_batched(radon_plan_t plan, int batch, const float* imgs_dev,

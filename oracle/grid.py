@@ -38,8 +38,8 @@ from .exact import ray_synthesis_matrix
 from .geometry import polar_uv
 from .kb import deapod_factors, kb_beta, kb_phi
 
-__all__ = ["GridParams", "grid_forward", "grid_adjoint", "grid_fft2", "grid_interp",
-           "grid_spread", "ray_spectrum", "ray_synthesis"]
+__all__ = ["GridParams", "grid_forward", "grid_adjoint", "grid_fbp", "fbp_weights", "grid_fft2",
+           "grid_interp", "grid_spread", "ray_spectrum", "ray_synthesis"]
 
 # FFT worker threads: the CPUs this process may use, at most 16 (the host
 # share of one GPU on the machines this runs on).
@@ -142,3 +142,38 @@ def grid_adjoint(y, angles, n: int, sigma: float = 2.0, W: int = 6) -> np.ndarra
     r = _pad_index(n, gp.G)
     return h[np.ix_(r, r)].real / (gp.psi[:, None] * gp.psi[None, :])
 
+
+
+def fbp_weights(n_views: int, n_det: int) -> np.ndarray:
+    """Ramp weights w_q of the filtered adjoint, q = -N/2..N/2-1.
+
+    The 2D inverse Fourier integral over the polar samples uses the area
+    element |rho| drho dtheta, dtheta = pi/n_views over [0, pi). The ramp
+    |rho| is taken as the DFT of the band-limited spatial ramp kernel
+    (Ramachandran-Lakshminarayanan): h[0] = 1/4, h[k] = -1/(pi k)^2 for odd k,
+    0 for even k != 0, on the N-periodic window |k| < N/2. It equals |q|/N up
+    to a few per cent and gives the DC term its correct small weight.
+    """
+    k = np.arange(n_det) - n_det // 2
+    h = np.zeros(n_det)
+    h[n_det // 2] = 0.25
+    odd = (k % 2) != 0
+    h[odd] = -1.0 / (np.pi * k[odd]) ** 2
+    H = np.fft.fft(np.fft.ifftshift(h)).real          # index q mod N
+    return (np.pi / n_views) * np.fft.fftshift(H)       # q = -N/2 .. N/2-1
+
+
+def grid_fbp(y, angles, n: int, sigma: float = 2.0, W: int = 6) -> np.ndarray:
+    """Filtered adjoint (filtered back-projection through the Fourier slice
+    theorem): the O-grid adjoint with the ray spectra weighted by fbp_weights.
+    The paper's 'standard tomographic processing' of the projections
+    (introduction) is read as this reconstruction."""
+    y = np.asarray(y, dtype=np.float64)
+    n_views, n_det = y.shape
+    gp = GridParams(n, n_det, sigma, W)
+    u, v = polar_uv(angles, n_det, gp.G)
+    Yhat = ray_spectrum(y, n_det) * fbp_weights(n_views, n_det)[None, :]
+    H = grid_spread(Yhat, u, v, gp)
+    h = sfft.ifft2(H, workers=_WORKERS) * (gp.G * gp.G)
+    r = _pad_index(n, gp.G)
+    return h[np.ix_(r, r)].real / (gp.psi[:, None] * gp.psi[None, :])

@@ -5,13 +5,14 @@
 
 namespace rn {
 
-hipError_t launch_a1(const Plan& p, const float* sino, hipStream_t st) {
+hipError_t launch_a1(const Plan& p, const float* sino, bool filtered, hipStream_t st) {
+    const float* wq = filtered ? p.fbpw : nullptr;
     const dim3 grid((p.n_views + 1) / 2);
     switch (p.n_det) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
         constexpr int NT = fft_threads(L, 1);                                                  \
-        hipLaunchKernelGGL((k_a1_rays<L, NT>), grid, dim3(NT), 0, st, sino, p.Yh, p.tw_N,       \
+        hipLaunchKernelGGL((k_a1_rays<L, NT>), grid, dim3(NT), 0, st, sino, p.Yh, p.tw_N, wq,   \
                            p.n_views);                                                         \
         break;                                                                                 \
     }

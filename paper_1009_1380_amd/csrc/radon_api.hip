@@ -101,6 +101,20 @@ void kb_cubic_piece(int i, int S, int W, double beta, double c[4]) {
     for (int j = 0; j < 4; ++j) c[j] = A[j][4] / A[j][j];
 }
 
+// Ramp weights of the filtered adjoint for q = 0..N/2: (pi/n_views) times the
+// DFT of the band-limited spatial ramp kernel h[0] = 1/4, h[k] = -1/(pi k)^2
+// (odd k), 0 (even k), on |k| < N/2, as a cosine series in float64.
+std::vector<float> ramp_weights(int n_views, int N) {
+    std::vector<float> w(N / 2 + 1);
+    for (int q = 0; q <= N / 2; ++q) {
+        double H = 0.25;
+        for (int k = 1; k < N / 2; k += 2)
+            H -= 2.0 * cos(2.0 * M_PI * (double)q * k / N) / ((M_PI * k) * (M_PI * k));
+        w[q] = (float)(M_PI / n_views * H);
+    }
+    return w;
+}
+
 bool is_supported_length(int len) { return rn::length_supported(len); }
 
 template <class T>
@@ -197,18 +211,19 @@ radon_status_t run_forward(Plan& p, const float* img, float* sino, hipStream_t s
     return RADON_OK;
 }
 
-radon_status_t run_adjoint_grid(Plan& p, const float* sino, hipStream_t st) {
+radon_status_t run_adjoint_grid(Plan& p, const float* sino, hipStream_t st, bool filtered = false) {
     radon_status_t s;
-    if ((s = launch_status(staged(p, rn::ST_A1, st, [&] { return rn::launch_a1(p, sino, st); }), "A1"))) return s;
+    if ((s = launch_status(staged(p, rn::ST_A1, st, [&] { return rn::launch_a1(p, sino, filtered, st); }), "A1")))
+        return s;
     if ((s = launch_status(staged(p, rn::ST_A2, st, [&] { return rn::launch_a2(p, st); }), "A2"))) return s;
     if (p.n_splits > 0)
         if ((s = launch_status(staged(p, rn::ST_A2R, st, [&] { return rn::launch_a2_reduce(p, st); }), "A2 reduce"))) return s;
     return RADON_OK;
 }
 
-radon_status_t run_adjoint(Plan& p, const float* sino, float* img, hipStream_t st) {
+radon_status_t run_adjoint(Plan& p, const float* sino, float* img, hipStream_t st, bool filtered = false) {
     radon_status_t s;
-    if ((s = run_adjoint_grid(p, sino, st))) return s;
+    if ((s = run_adjoint_grid(p, sino, st, filtered))) return s;
     if ((s = launch_status(staged(p, rn::ST_A3, st, [&] { return rn::launch_a3(p, st); }), "A3"))) return s;
     if ((s = launch_status(staged(p, rn::ST_A4, st, [&] { return rn::launch_a4(p, img, st); }), "A4"))) return s;
     return RADON_OK;
@@ -374,6 +389,7 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
     if ((s = dev_alloc(p, &p.tw_n, n)) || (s = upload(p.tw_n, twiddles(n)))) return s;
     if ((s = dev_alloc(p, &p.tw_N, n_det)) || (s = upload(p.tw_N, twiddles(n_det)))) return s;
     if ((s = dev_alloc(p, &p.kbc, kbc.size())) || (s = upload(p.kbc, kbc))) return s;
+    if ((s = dev_alloc(p, &p.fbpw, n_det / 2 + 1)) || (s = upload(p.fbpw, ramp_weights(n_views, n_det)))) return s;
     if ((s = dev_alloc(p, &p.perm, (size_t)p.n_samples))) return s;
     if ((s = dev_alloc(p, &p.offs4, (size_t)4 * p.n_bins + 1))) return s;
     std::vector<int> offs;
@@ -480,6 +496,14 @@ radon_status_t radon_adjoint(radon_plan_t plan, const float* sino_dev, float* im
     if ((s = check_plan(plan))) return s;
     if (!img_dev || !sino_dev) return fail(RADON_ERR_INVALID, "NULL buffer");
     if ((s = run_adjoint(plan->p, sino_dev, img_dev, (hipStream_t)stream))) return s;
+    return ok();
+}
+
+radon_status_t radon_fbp(radon_plan_t plan, const float* sino_dev, float* img_dev, void* stream) {
+    radon_status_t s;
+    if ((s = check_plan(plan))) return s;
+    if (!img_dev || !sino_dev) return fail(RADON_ERR_INVALID, "NULL buffer");
+    if ((s = run_adjoint(plan->p, sino_dev, img_dev, (hipStream_t)stream, true))) return s;
     return ok();
 }
 

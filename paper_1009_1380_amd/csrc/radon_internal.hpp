@@ -52,6 +52,7 @@ struct Plan {
     float2* tw_n = nullptr;      // e^{-2 pi i t/n}, n
     float2* tw_N = nullptr;      // e^{-2 pi i t/N}, N
     float4* kbc = nullptr;       // cubic pieces of phi on [0, W/2]
+    float* fbpw = nullptr;       // ramp weights of the filtered adjoint, q = 0..N/2
     // device workspace
     float2* T1 = nullptr;        // (n+1) x n complex64
     float2* grid = nullptr;      // (n+1) x G complex64
@@ -78,7 +79,7 @@ hipError_t launch_f1(const Plan& p, const float* img, hipStream_t st);
 hipError_t launch_f2(const Plan& p, hipStream_t st);
 hipError_t launch_f3(const Plan& p, hipStream_t st);
 hipError_t launch_f4(const Plan& p, float* sino, hipStream_t st);
-hipError_t launch_a1(const Plan& p, const float* sino, hipStream_t st);
+hipError_t launch_a1(const Plan& p, const float* sino, bool filtered, hipStream_t st);
 hipError_t launch_a2(const Plan& p, hipStream_t st);
 hipError_t launch_a2_reduce(const Plan& p, hipStream_t st);
 hipError_t launch_a3(const Plan& p, hipStream_t st);

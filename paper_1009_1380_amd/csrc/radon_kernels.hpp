@@ -379,10 +379,13 @@ __global__ __launch_bounds__(NT) void k_f4_rays(const float2* __restrict__ Xr, f
 // ---------------------------------------------------------------- A1
 // Two rays per workgroup: Yhat_a[q] = (1/N) sum_d y[a,d] e^{-2 pi i q s_d/N},
 // q = 0..N/2; the q = N/2 (Nyquist) value is halved because it is spread
-// once at its own position and once at the mirrored one.
+// once at its own position and once at the mirrored one. With a weight
+// table wq (the ramp of the filtered adjoint) Yhat_a[q] is multiplied by
+// wq[q]; wq = nullptr gives the plain adjoint.
 template <int ND, int NT>
 __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, float2* __restrict__ Yh,
-                                               const float2* __restrict__ tw, int n_views) {
+                                               const float2* __restrict__ tw, const float* __restrict__ wq,
+                                               int n_views) {
     constexpr int HQ = ND / 2 + 1;
     __shared__ float2 lds[lds_ls(ND)];
     const int tid = threadIdx.x;
@@ -399,7 +402,8 @@ __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, 
         const float2 zq = lds[lds_pad(q)];
         const float2 zc = cconj(lds[lds_pad((ND - q) % ND)]);
         const float2 sm = cadd(zq, zc), df = csub(zq, zc);
-        const float h = (q == ND / 2) ? 0.5f * sc : sc;
+        float h = (q == ND / 2) ? 0.5f * sc : sc;
+        if (wq) h *= wq[q];
         if (a0 < n_views) Yh[(size_t)a0 * HQ + q] = make_float2(h * sm.x, h * sm.y);
         if (a0 + 1 < n_views) Yh[(size_t)(a0 + 1) * HQ + q] = make_float2(h * df.y, -h * df.x);
     }

@@ -31,6 +31,7 @@ _SIGS = {
     "radon_plan": (_c_int, [ctypes.POINTER(_vp), _c_int, ctypes.POINTER(_c_dbl), _c_int, _c_int, _c_dbl, _c_int]),
     "radon_forward": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_adjoint": (_c_int, [_vp, _vp, _vp, _vp]),
+    "radon_fbp": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_forward_batched": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
     "radon_adjoint_batched": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
     "radon_plan_sort_indices": (_c_int, [_vp, _vp, _c_i64, _vp, _c_i64]),
@@ -185,6 +186,16 @@ class Plan:
         _check(lib().radon_adjoint(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
                                    _dev_ptr(out, (self.n, self.n), "out"), _stream_ptr(stream)),
                "radon_adjoint")
+        return out
+
+    def fbp(self, sino, out=None, stream=None):
+        """Filtered adjoint (ramp-weighted back-projection)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n, self.n), dtype=torch.float32, device=sino.device)
+        _check(lib().radon_fbp(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
+                               _dev_ptr(out, (self.n, self.n), "out"), _stream_ptr(stream)),
+               "radon_fbp")
         return out
 
     def forward_batched(self, imgs, out=None, stream=None):

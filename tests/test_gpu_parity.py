@@ -340,3 +340,28 @@ def test_full_size_adjoint_identity_and_determinism():
     lhs = float(torch.sum(Ax.double() * y.double()))
     rhs = float(torch.sum(x.double() * Aty.double()))
     assert abs(lhs - rhs) <= 1e-5 * float(torch.linalg.norm(Ax.double())) * float(torch.linalg.norm(y.double()))
+
+
+# ------------------------------------------------------------------ filtered adjoint
+
+@pytest.mark.parametrize("n,n_det,nv", [(16, 16, 9), (64, 80, 31), (128, 128, 180)])
+def test_fbp_vs_oracle(n, n_det, nv):
+    from oracle.grid import grid_fbp
+    note(f"fbp n={n} n_det={n_det} nv={nv}")
+    ang = special_angles(nv, 7) if nv != 180 else uniform_angles(nv)
+    y = random_sinogram(71, nv, n_det)
+    plan = Plan(n, ang, n_det)
+    r = plan.fbp(to_dev(y)).cpu().numpy()
+    assert rel(r, grid_fbp(y.astype(np.float64), ang, n)) < TOL_GRID
+
+
+def test_fbp_reconstructs_gaussian():
+    note("fbp gaussian")
+    n = 256
+    x = (gaussian_blob(n, 7.3, -5.1, 4.0) + 0.5 * gaussian_blob(n, -12.0, 9.0, 3.0)).astype(np.float32)
+    ang = uniform_angles(2 * n)
+    plan = Plan(n, ang, n)
+    r = plan.fbp(plan.forward(to_dev(x))).cpu().numpy()
+    xs = np.arange(n) - n / 2
+    inside = np.sqrt(xs[None, :] ** 2 + xs[:, None] ** 2) < n / 2 - 2
+    assert rel(r[inside], x[inside]) < 3e-4
