@@ -1,0 +1,105 @@
+"""Pins for the oracle's ring filter, l1-ball projection and SPGL1 solver.
+
+The ring filter is pinned by its algebra (symmetric projection that removes
+angle-independent non-cubic detector patterns and keeps cubic ones), the
+projection by an independent bisection on the threshold, and the solver by
+a linear-programming solution of basis pursuit (scipy's HiGHS) and by the
+optimality conditions of basis-pursuit denoising.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import linprog
+
+from oracle.solver import cubic_basis, project_l1, ring_filter, spgl1_bpdn
+
+
+def test_cubic_basis_spans_cubics():
+    N = 40
+    Q = cubic_basis(N)
+    assert np.allclose(Q.T @ Q, np.eye(4), atol=1e-12)
+    s = np.arange(N) - N / 2
+    cubic = 0.3 - 0.02 * s + 1e-3 * s ** 2 + 2e-5 * s ** 3
+    assert np.allclose(Q @ (Q.T @ cubic), cubic, atol=1e-12)
+    # a non-polynomial profile is not in the span; its residual matches polyfit
+    g = np.cos(0.9 * s)
+    res = g - Q @ (Q.T @ g)
+    fit = np.polyval(np.polyfit(s, g, 3), s)
+    assert np.allclose(res, g - fit, atol=1e-10)
+
+
+def test_ring_filter_algebra():
+    rng = np.random.default_rng(0)
+    nv, N = 17, 32
+    y, z = rng.standard_normal((nv, N)), rng.standard_normal((nv, N))
+    Fy = ring_filter(y)
+    assert abs(np.sum(Fy * z) - np.sum(y * ring_filter(z))) < 1e-12      # symmetric
+    assert np.allclose(ring_filter(Fy), Fy, atol=1e-12)                  # idempotent
+    s = np.arange(N) - N / 2
+    g = rng.standard_normal(N)
+    Q = cubic_basis(N)
+    ring = g - Q @ (Q.T @ g)                                             # non-cubic stripe profile
+    assert np.allclose(ring_filter(np.tile(ring, (nv, 1))), 0.0, atol=1e-12)
+    smooth = np.tile(1.0 + 0.01 * s - 1e-4 * s ** 3, (nv, 1))
+    assert np.allclose(ring_filter(smooth), smooth, atol=1e-12)
+    zero_mean = y - y.mean(axis=0)
+    assert np.allclose(ring_filter(zero_mean), zero_mean, atol=1e-12)
+
+
+def _proj_bisect(x, tau):
+    lo, hi = 0.0, np.abs(x).max()
+    for _ in range(200):
+        lam = 0.5 * (lo + hi)
+        if np.maximum(np.abs(x) - lam, 0).sum() > tau:
+            lo = lam
+        else:
+            hi = lam
+    return np.sign(x) * np.maximum(np.abs(x) - 0.5 * (lo + hi), 0)
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.3, 2.0, 7.5, 100.0])
+def test_project_l1(tau):
+    x = np.random.default_rng(1).standard_normal(50)
+    p = project_l1(x, tau)
+    if np.abs(x).sum() <= tau:
+        assert np.array_equal(p, x)
+    else:
+        assert abs(np.abs(p).sum() - tau) <= 1e-12 * max(1, tau)
+        assert np.allclose(p, _proj_bisect(x, tau), atol=1e-12)
+
+
+def _random_cs(seed, m=60, n=200, k=8):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) / np.sqrt(m)
+    x0 = np.zeros(n)
+    x0[rng.choice(n, k, replace=False)] = rng.standard_normal(k)
+    return A, x0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_basis_pursuit_matches_linear_program(seed):
+    A, x0 = _random_cs(seed)
+    b = A @ x0
+    x, info = spgl1_bpdn(lambda v: A @ v, lambda r: A.T @ r, b, 0.0, opt_tol=1e-6, max_iter=20000)
+    assert info["status"] == "bp"
+    n = A.shape[1]
+    lp = linprog(np.ones(2 * n), A_eq=np.hstack([A, -A]), b_eq=b, bounds=(0, None), method="highs")
+    assert lp.status == 0
+    assert abs(np.abs(x).sum() - lp.fun) <= 1e-6 * lp.fun
+    assert np.linalg.norm(x - x0) <= 1e-4 * np.linalg.norm(x0)     # exact sparse recovery
+
+
+def test_bpdn_optimality_conditions():
+    A, x0 = _random_cs(3)
+    rng = np.random.default_rng(4)
+    e = 0.01 * rng.standard_normal(A.shape[0])
+    b = A @ x0 + e
+    sigma = float(np.linalg.norm(e))
+    x, info = spgl1_bpdn(lambda v: A @ v, lambda r: A.T @ r, b, sigma, opt_tol=1e-7, max_iter=20000)
+    assert info["status"] == "root"
+    r = b - A @ x
+    assert abs(np.linalg.norm(r) - sigma) <= 1e-6 * sigma
+    g = A.T @ r
+    lam = np.abs(g).max()
+    sup = np.abs(x) > 1e-9
+    assert np.abs(g[sup] - lam * np.sign(x[sup])).max() <= 1e-2 * lam   # active set on the boundary
+    assert np.abs(g[~sup]).max() <= lam * (1 + 1e-9)
