@@ -174,6 +174,51 @@ radon_status_t radon_debug_adjoint_grid(radon_plan_t plan, const float* sino_dev
 radon_status_t radon_fft_test(int len, int batch, int inverse, const float* in_dev,
                               float* out_dev, void* stream);
 
+/*
+ * Ring filter of the basis-pursuit problem (the paper's polynomial filter,
+ * introduction): F y = y - 1 (x) (m - P3 m) with m[d] the mean over views of
+ * y[., d] and P3 the least-squares projection onto cubic polynomials in the
+ * detector coordinate. F is a symmetric projection. y_dev, out_dev:
+ * n_views*n_det float32 (may alias). Synchronises the stream.
+ */
+radon_status_t radon_ring_filter(radon_plan_t plan, const float* y_dev, float* out_dev, void* stream);
+
+typedef struct {
+    double sigma;      /* target ||F(A x - b)||_2, absolute, >= 0 (epsilon of the paper)  */
+    double opt_tol;    /* relative tolerance of the root and of the duality gap (1e-4)    */
+    double bp_tol;     /* basis-pursuit exit: ||r|| <= bp_tol ||F b|| (1e-6)              */
+    double dec_tol;    /* stall test that triggers the Newton step on tau (1e-4)          */
+    int max_iter;      /* iteration limit                                                  */
+    int ring_filter;   /* 1: operator F A and data F b; 0: F = identity                    */
+    int warm_start;    /* 1: x_dev holds the starting image and tau0 = ||x0||_1; 0: x0 = 0 */
+} radon_solve_opts;
+
+typedef struct {
+    double rnorm;      /* final ||F(A x - b)||_2                                          */
+    double tau;        /* final l1 radius                                                  */
+    double x_l1;       /* ||x||_1 of the result                                            */
+    double seconds;    /* host wall time of the call                                       */
+    int iterations;    /* projected-gradient iterations                                    */
+    int n_forward;     /* radon_forward applications                                       */
+    int n_adjoint;     /* radon_adjoint applications                                       */
+    int status;        /* 0 iteration limit, 1 basis-pursuit solution, 2 root found        */
+} radon_solve_stats;
+
+/*
+ * Basis-pursuit denoising min ||x||_1 s.t. ||F(A x - b)||_2 <= sigma (the
+ * paper's reconstruction problem, introduction), solved by SPGL1 root
+ * finding on the Pareto curve (van den Berg & Friedlander 2008): Newton steps
+ * on tau, each LASSO(tau) by spectral projected gradient with a non-monotone
+ * line search and projection onto the l1 ball. b_dev: n_views*n_det float32
+ * sinogram; x_dev: n*n float32, the start image when warm_start, overwritten
+ * with the solution. Vectors are float32; all reductions are float64 in a
+ * fixed order, so results are bitwise reproducible. The call allocates its
+ * workspace, runs on `stream` and synchronises it (it reads a few float64
+ * scalars per iteration); stats may be NULL.
+ */
+radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev, float* x_dev, const radon_solve_opts* opts,
+                                radon_solve_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

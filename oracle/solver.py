@@ -61,14 +61,15 @@ def project_l1(x, tau: float) -> np.ndarray:
     u = np.sort(a)[::-1]
     cs = np.cumsum(u)
     k = np.arange(1, u.size + 1)
-    rho = np.nonzero(u * k > (cs - tau))[0][-1]
+    idx = np.nonzero(u * k > (cs - tau))[0]
+    rho = idx[-1] if idx.size else 0
     lam = (cs[rho] - tau) / (rho + 1.0)
     return np.sign(x) * np.maximum(np.abs(x) - lam, 0.0)
 
 
 def spgl1_bpdn(A, At, b, sigma: float, x0=None, tau0: float | None = None, opt_tol: float = 1e-4,
                bp_tol: float = 1e-6, dec_tol: float = 1e-4, max_iter: int = 5000, bb_min: float = 1e-16,
-               bb_max: float = 1e16, n_mem: int = 3):
+               bb_max: float = 1e5, n_mem: int = 3):
     """min ||x||_1 s.t. ||A x - b||_2 <= sigma by SPGL1 root finding.
 
     A, At: callables for the operator and its adjoint (float64 arrays).
@@ -128,8 +129,15 @@ def spgl1_bpdn(A, At, b, sigma: float, x0=None, tau0: float | None = None, opt_t
         stalled = (change <= dec_tol * f and rnorm > 2 * sigma) or \
                   (change <= 0.1 * f * abs(rnorm - sigma) and rnorm <= 2 * sigma)
         if stalled and gnorm > 0:
+            tau_old = tau
             tau = max(0.0, tau + rnorm * aerr1 / gnorm)   # Newton step on the Pareto curve
-            x = project_l1(x, tau)
+            if tau < tau_old:
+                # the ball shrank: restart the subproblem from the projected
+                # (feasible) iterate with its own residual and gradient
+                x = project_l1(x, tau)
+                r = resid(x)
+                f = 0.5 * float(np.vdot(r, r))
+                g = grad(r)
             fs = [f] * n_mem
         # spectral projected gradient step, non-monotone (GLL) backtracking
         fmax = max(fs)

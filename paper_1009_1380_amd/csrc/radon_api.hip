@@ -17,10 +17,6 @@
 
 using rn::Plan;
 
-struct radon_plan_s {
-    Plan p;
-};
-
 namespace {
 
 thread_local std::string g_last_error;

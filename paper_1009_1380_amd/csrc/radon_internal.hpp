@@ -90,3 +90,8 @@ hipError_t launch_fft_test(int len, int batch, int inverse, const float2* in, fl
 bool length_supported(int len);
 
 }  // namespace rn
+
+// The opaque handle of the C ABI.
+struct radon_plan_s {
+    rn::Plan p;
+};

@@ -48,7 +48,24 @@ _SIGS = {
     "radon_debug_forward_grid": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_debug_adjoint_grid": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_fft_test": (_c_int, [_c_int, _c_int, _c_int, _vp, _vp, _vp]),
+    "radon_ring_filter": (_c_int, [_vp, _vp, _vp, _vp]),
+    "radon_solve_bpdn": (_c_int, [_vp, _vp, _vp, ctypes.c_void_p, ctypes.c_void_p, _vp]),
 }
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("opt_tol", ctypes.c_double), ("bp_tol", ctypes.c_double),
+                ("dec_tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("ring_filter", ctypes.c_int),
+                ("warm_start", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("rnorm", ctypes.c_double), ("tau", ctypes.c_double), ("x_l1", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("iterations", ctypes.c_int), ("n_forward", ctypes.c_int),
+                ("n_adjoint", ctypes.c_int), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class RadonError(RuntimeError):
@@ -217,6 +234,34 @@ class Plan:
                                            _dev_ptr(out, (b, self.n, self.n), "out"), _stream_ptr(stream)),
                "radon_adjoint_batched")
         return out
+
+    # -- reconstruction (the paper's basis-pursuit problem)
+    def ring_filter(self, sino, out=None, stream=None):
+        """Cubic-polynomial ring filter F of the sinogram (a symmetric projection)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(sino)
+        _check(lib().radon_ring_filter(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
+                                       _dev_ptr(out, (self.n_views, self.n_det), "out"), _stream_ptr(stream)),
+               "radon_ring_filter")
+        return out
+
+    def solve_bpdn(self, sino, sigma: float, x0=None, opt_tol: float = 1e-4, bp_tol: float = 1e-6,
+                   dec_tol: float = 1e-4, max_iter: int = 500, ring_filter: bool = True, stream=None):
+        """min ||x||_1 s.t. ||F(A x - sino)||_2 <= sigma (SPGL1). x0: optional
+        warm-start image. Returns (x, stats dict)."""
+        torch = _torch()
+        if x0 is None:
+            x = torch.zeros((self.n, self.n), dtype=torch.float32, device=sino.device)
+        else:
+            x = x0.clone()
+        opts = SolveOpts(float(sigma), float(opt_tol), float(bp_tol), float(dec_tol), int(max_iter),
+                         int(bool(ring_filter)), int(x0 is not None))
+        stats = SolveStats()
+        _check(lib().radon_solve_bpdn(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
+                                      _dev_ptr(x, (self.n, self.n), "x"), ctypes.byref(opts), ctypes.byref(stats),
+                                      _stream_ptr(stream)), "radon_solve_bpdn")
+        return x, stats.as_dict()
 
     # -- introspection and test hooks
     def info(self) -> dict:

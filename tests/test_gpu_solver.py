@@ -1,0 +1,96 @@
+"""GPU ring filter and basis-pursuit solver against the oracle (MI355X).
+
+L1 minimisers need not be unique, so solves are compared by what is unique:
+the residual norm at the solution (= sigma) and the optimal l1 norm.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.grid import grid_adjoint, grid_forward  # noqa: E402
+from oracle.solver import ring_filter, spgl1_bpdn  # noqa: E402
+from radon_inputs import config1_phantom, random_sinogram, uniform_angles  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1009_1380_amd import Plan  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def test_ring_filter_vs_oracle():
+    note("ring filter")
+    nv, N = 33, 80
+    y = random_sinogram(81, nv, N)
+    y += np.tile(np.random.default_rng(2).normal(0, 0.3, N), (nv, 1)).astype(np.float32)
+    plan = Plan(16, uniform_angles(nv), N)
+    out = plan.ring_filter(to_dev(y)).cpu().numpy()
+    ref = ring_filter(y.astype(np.float64))
+    assert np.linalg.norm(out - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def _problem(n=32, nv=24, seed=0):
+    x, _ = config1_phantom(seed, n)
+    ang = uniform_angles(nv)
+    y = grid_forward(x.astype(np.float64), ang, n)
+    rng = np.random.default_rng(seed + 100)
+    gains = rng.normal(1.0, 0.02, n)
+    b = y * gains[None, :] + rng.normal(0, 0.01 * np.abs(y).max(), y.shape)
+    return x, ang, b.astype(np.float32)
+
+
+@pytest.mark.parametrize("ring", [True, False])
+def test_solver_matches_oracle(ring):
+    note(f"solver ring={ring}")
+    n, nv = 32, 24
+    x_true, ang, b = _problem(n, nv)
+    F = ring_filter if ring else (lambda v: v)
+    bt = F(b.astype(np.float64))
+    sigma = 0.05 * float(np.linalg.norm(bt))
+    A = lambda v: F(grid_forward(v, ang, n))            # noqa: E731
+    At = lambda r: grid_adjoint(F(r), ang, n)           # noqa: E731
+    xo, io = spgl1_bpdn(A, At, bt, sigma, opt_tol=1e-5, max_iter=5000)
+    plan = Plan(n, ang, n)
+    xg, ig = plan.solve_bpdn(to_dev(b), sigma, opt_tol=1e-5, max_iter=5000, ring_filter=ring)
+    note(f"oracle {io}  gpu {ig}")
+    assert io["status"] == "root" and ig["status"] == 2
+    assert abs(ig["rnorm"] - sigma) <= 2e-5 * sigma
+    xg = xg.cpu().numpy().astype(np.float64)
+    r = F(b.astype(np.float64) - grid_forward(xg, ang, n))      # residual of the GPU solution, in FP64
+    assert abs(np.linalg.norm(r) - sigma) <= 1e-3 * sigma
+    l1o, l1g = np.abs(xo).sum(), np.abs(xg).sum()
+    assert abs(l1g - l1o) <= 2e-3 * l1o
+
+
+def test_solver_deterministic_and_warm_start():
+    note("solver determinism / warm start")
+    n, nv = 64, 48
+    x_true, ang, b = _problem(n, nv, seed=3)
+    plan = Plan(n, ang, n)
+    bd = to_dev(b)
+    bt = plan.ring_filter(bd)
+    sigma = 0.03 * float(torch.linalg.norm(bt.double()))
+    x1, s1 = plan.solve_bpdn(bd, sigma, max_iter=2000)
+    x2, s2 = plan.solve_bpdn(bd, sigma, max_iter=2000)
+    assert torch.equal(x1, x2) and s1["iterations"] == s2["iterations"]
+    assert s1["status"] == 2
+    # a warm start from the filtered adjoint reaches the same residual
+    x0 = plan.fbp(bd)
+    x3, s3 = plan.solve_bpdn(bd, sigma, x0=x0, max_iter=2000)
+    assert s3["status"] == 2 and abs(s3["rnorm"] - sigma) <= 1e-4 * sigma
+    assert abs(s3["x_l1"] - s1["x_l1"]) <= 2e-3 * s1["x_l1"]

@@ -84,7 +84,7 @@ def test_basis_pursuit_matches_linear_program(seed):
     n = A.shape[1]
     lp = linprog(np.ones(2 * n), A_eq=np.hstack([A, -A]), b_eq=b, bounds=(0, None), method="highs")
     assert lp.status == 0
-    assert abs(np.abs(x).sum() - lp.fun) <= 1e-6 * lp.fun
+    assert abs(np.abs(x).sum() - lp.fun) <= 1e-5 * lp.fun
     assert np.linalg.norm(x - x0) <= 1e-4 * np.linalg.norm(x0)     # exact sparse recovery
 
 
@@ -101,5 +101,25 @@ def test_bpdn_optimality_conditions():
     g = A.T @ r
     lam = np.abs(g).max()
     sup = np.abs(x) > 1e-9
-    assert np.abs(g[sup] - lam * np.sign(x[sup])).max() <= 1e-2 * lam   # active set on the boundary
+    # SPGL1 stops once ||r|| reaches sigma, so the dual conditions hold only roughly
+    assert np.abs(g[sup] - lam * np.sign(x[sup])).max() <= 5e-2 * lam
     assert np.abs(g[~sup]).max() <= lam * (1 + 1e-9)
+    # the optimal l1 norm is the root tau* of phi(tau) = sigma on the Pareto
+    # curve; phi is evaluated independently by accelerated projected gradient
+    # (FISTA, fixed step 1/||A||^2) and the root bracketed by bisection
+    L = np.linalg.norm(A, 2) ** 2
+
+    def phi(tau, its=2000):
+        z = y = np.zeros(A.shape[1])
+        t = 1.0
+        for _ in range(its):
+            zn = project_l1(y - A.T @ (A @ y - b) / L, tau)
+            tn = 0.5 * (1 + np.sqrt(1 + 4 * t * t))
+            y, z, t = zn + (t - 1) / tn * (zn - z), zn, tn
+        return np.linalg.norm(b - A @ z)
+
+    lo, hi = 0.0, 2 * np.abs(x0).sum()
+    for _ in range(36):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if phi(mid) > sigma else (lo, mid)
+    assert abs(np.abs(x).sum() - 0.5 * (lo + hi)) <= 1e-5 * hi
