@@ -25,6 +25,8 @@ __all__ = [
     "gaussian_blob",
     "config1_phantom",
     "config2_phantom",
+    "disk_sinogram",
+    "config4_problem",
     "random_sinogram",
     "random_image",
 ]
@@ -120,3 +122,36 @@ def random_image(seed: int, n: int) -> np.ndarray:
 def random_sinogram(seed: int, n_views: int, n_det: int) -> np.ndarray:
     """i.i.d. U(-1, 1) float32 sinogram (adjoint identity, parity)."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n_views, n_det)).astype(np.float32)
+
+
+def disk_sinogram(disks, angles, n_det: int) -> np.ndarray:
+    """Exact line integrals of the disks (float64, n_views x n_det): a disk of
+    radius r, density rho and centre c contributes rho * 2 sqrt(r^2 - t^2) at
+    detector s_d = d - n_det/2, t = s_d - (c_x cos th + c_y sin th)."""
+    angles = np.asarray(angles, dtype=np.float64)
+    s = np.arange(n_det, dtype=np.float64) - n_det / 2
+    c, sn = np.cos(angles)[:, None], np.sin(angles)[:, None]
+    out = np.zeros((angles.size, n_det))
+    for cx, cy, r, rho in disks:
+        t = s[None, :] - (cx * c + cy * sn)
+        out += rho * 2.0 * np.sqrt(np.maximum(r * r - t * t, 0.0))
+    return out
+
+
+def config4_problem(seed: int = 0, n: int = 1024, n_views: int = 128, n_det: int = 1024, k: int = 60,
+                    snr_db: float = 30.0, gain_sd: float = 0.02):
+    """Reduced-view reconstruction workload: an n x n piecewise-constant disk
+    phantom (k disks, radii U(8, n/8), densities U(0.5, 1)), measured at
+    n_views angles uniform in [0, pi) on n_det bins by exact line integrals,
+    each detector scaled by a gain N(1, gain_sd^2) (ring stripes), then i.i.d.
+    Gaussian noise at the given SNR (20 log10 ||signal|| / ||noise||).
+    Returns (float32 image, float32 sinogram, angles)."""
+    rng = np.random.default_rng(seed)
+    disks = disk_params(rng, n, k, 8.0, n / 8)
+    img = disk_phantom(n, disks)
+    ang = uniform_angles(n_views)
+    clean = disk_sinogram(disks, ang, n_det)
+    gains = rng.normal(1.0, gain_sd, size=n_det)
+    noise_sd = np.linalg.norm(clean) / np.sqrt(clean.size) * 10.0 ** (-snr_db / 20.0)
+    b = clean * gains[None, :] + rng.normal(0.0, noise_sd, size=clean.shape)
+    return img.astype(np.float32), b.astype(np.float32), ang
