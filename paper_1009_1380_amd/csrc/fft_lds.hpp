@@ -224,6 +224,17 @@ __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ 
 // with more threads: 512 from length 1024 on.
 constexpr int line_threads(int len) { return len >= 1024 ? 512 : (len >= 256 ? 256 : (len >= 64 ? 128 : 64)); }
 
+// Threads of the row kernels (F1, A4) and column kernels (F2, A3) for lines of
+// length 1024 and more (compile-time tuning knobs).
+#ifndef RN_ROW_NT
+#define RN_ROW_NT 1024
+#endif
+#ifndef RN_COL_NT
+#define RN_COL_NT 512
+#endif
+constexpr int row_threads(int len) { return len >= 1024 ? RN_ROW_NT : line_threads(len); }
+constexpr int col_threads(int len) { return len >= 1024 ? RN_COL_NT : line_threads(len); }
+
 constexpr int fft_threads(int len, int b) {
     int work = len * b / 8;
     return work >= 1024 ? 512 : (work >= 256 ? 256 : (work >= 128 ? 128 : 64));

@@ -68,7 +68,7 @@ hipError_t launch_a3(const Plan& p, hipStream_t st) {
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = line_threads(L);                                                  \
+        constexpr int NT = col_threads(L);                                                   \
         hipLaunchKernelGGL((k_a3_cols<L, NT>), grid, dim3(NT), 0, st, p.grid, p.T1, p.shift_n,  \
                            p.tw_n);                                                            \
         break;                                                                                 \
@@ -86,7 +86,7 @@ hipError_t launch_a4(const Plan& p, float* img, hipStream_t st) {
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = line_threads(L);                                                  \
+        constexpr int NT = row_threads(L);                                                   \
         hipLaunchKernelGGL((k_a4_rows<L, NT>), grid, dim3(NT), 0, st, p.T1, img, p.psi_inv,     \
                            p.shift_n, p.tw_n);                                                 \
         break;                                                                                 \

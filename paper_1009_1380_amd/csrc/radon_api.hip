@@ -38,11 +38,11 @@ radon_status_t ok() {
 
 // Visits per spreading work item; longer tile lists are split and their
 // partial tiles summed in a fixed order.
-constexpr int kA2Chunk = rn::A2_MAX_VISITS;
+constexpr int kA2Chunk = rn::A2_CHUNK;
 // Samples per forward interpolation work item.
 constexpr int kF3Chunk = 2048;
 // Cubic Kaiser-Bessel pieces per unit of t (a power of two).
-constexpr int kKbS = 32;
+constexpr int kKbS = rn::KB_S;
 
 // I0(x) by its power series sum ((x/2)^(2k) / (k!)^2); x <= 40 here.
 double bessel_i0(double x) {

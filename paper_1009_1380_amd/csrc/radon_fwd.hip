@@ -10,7 +10,7 @@ hipError_t launch_f1(const Plan& p, const float* img, hipStream_t st) {
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = line_threads(L);                                                  \
+        constexpr int NT = row_threads(L);                                                   \
         hipLaunchKernelGGL((k_f1_rows<L, NT>), grid, dim3(NT), 0, st, img, p.T1, p.psi_inv,     \
                            p.shift_n, p.tw_n);                                                 \
         break;                                                                                 \
@@ -28,7 +28,7 @@ hipError_t launch_f2(const Plan& p, hipStream_t st) {
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = line_threads(L);                                                  \
+        constexpr int NT = col_threads(L);                                                   \
         hipLaunchKernelGGL((k_f2_cols<L, NT>), grid, dim3(NT), 0, st, p.T1, p.grid, p.shift_n,  \
                            p.tw_n);                                                            \
         break;                                                                                 \

@@ -79,6 +79,13 @@ __device__ __forceinline__ int mod_pos(int a, int m) {
     return r < 0 ? r + m : r;
 }
 
+// a mod G for a in [-G, 2G) (one compare and add instead of an integer division).
+__device__ __forceinline__ int wrap_g(int a, int G) { return a < 0 ? a + G : (a >= G ? a - G : a); }
+
+// Cubic pieces of the Kaiser-Bessel table per unit of t (the host builds the
+// table with the same count).
+constexpr int KB_S = 32;
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2). Renumber block b of nb so that each XCD gets a contiguous run of
 // logical blocks: neighbouring blocks, which share cache lines, then run
@@ -207,8 +214,13 @@ __global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, f
 // M..M+n_views-1 are the mirrored Nyquist samples (view a at q = +N/2).
 __device__ __forceinline__ void decode_sample(int v, int M, int ND, int& a, int& q) {
     if (v < M) {
-        a = v / ND;
-        q = v - a * ND - ND / 2;
+        // a = v / ND: the float64 quotient (v < 2^30) is within one of the
+        // integer one, then one correction step each way makes it exact
+        a = (int)((double)v * (1.0 / (double)ND));
+        int r = v - a * ND;
+        if (r < 0) { --a; r += ND; }
+        if (r >= ND) { ++a; r -= ND; }
+        q = r - ND / 2;
     } else {
         a = v - M;
         q = ND / 2;
@@ -216,7 +228,8 @@ __device__ __forceinline__ void decode_sample(int v, int M, int ND, int& a, int&
 }
 
 // Centred grid coordinate of the first footprint point: (floor - W/2 + 1 + G/2) mod G.
-__device__ __forceinline__ int footprint_origin(int b, int W, int G) { return mod_pos(b - W / 2 + 1 + G / 2, G); }
+// (b is floor(u) or floor(v), within [-G/2 - 1, G/2]).
+__device__ __forceinline__ int footprint_origin(int b, int W, int G) { return wrap_g(b - W / 2 + 1 + G / 2, G); }
 
 // Tile columns whose samples the forward interpolates: the Hermitian half
 // plane mx in [0, G/2] (centred columns ntl/2..ntl-1 and column 0, which
@@ -257,7 +270,9 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
                                                 const double2* __restrict__ cs, const float4* __restrict__ kbc,
                                                 float kbS, float2* __restrict__ Xr, int G, int ND, int n_views) {
     constexpr int P = 2 * T + W - 1;
+    constexpr int NKB = (W / 2) * KB_S;
     __shared__ float2 tile[P * P];   // [lx][ly], lx along u (mx), ly along v (my)
+    __shared__ float4 kbt[NKB];
     const int tid = threadIdx.x;
     const F3Item it = items[blockIdx.x];
     const int x0 = it.cx * T, y0 = it.cy * T;
@@ -273,17 +288,18 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
     const int s2 = offs4[4 * b2], n2 = offs4[4 * b2 + 4] - s2;
     const int s3 = offs4[4 * b3];
 
-    // stage the super-tile
+    // stage the kernel table and the super-tile
+    for (int e = tid; e < NKB; e += NT) kbt[e] = kbc[e];
     for (int e = tid; e < P * P; e += NT) {
         const int lx = e / P, ly = e - lx * P;
-        int mx = mod_pos(x0 + lx, G) - G / 2;        // in [-G/2, G/2)
-        const int my = mod_pos(y0 + ly, G) - G / 2;
+        int mx = wrap_g(x0 + lx, G) - G / 2;        // in [-G/2, G/2)
+        const int my = wrap_g(y0 + ly, G) - G / 2;
         if (mx == -G / 2) mx = G / 2;
         float2 val;
         if (mx >= 0) {
-            val = grid[(size_t)mx * G + mod_pos(my, G)];
+            val = grid[(size_t)mx * G + wrap_g(my, G)];
         } else {
-            val = cconj(grid[(size_t)(-mx) * G + mod_pos(-my, G)]);
+            val = cconj(grid[(size_t)(-mx) * G + wrap_g(-my, G)]);
         }
         tile[e] = val;
     }
@@ -312,16 +328,16 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
             conj_out = true;
         }
         const SampleGeom g = sample_geom(csa.x, csa.y, q, G, ND);
-        const int ox = mod_pos(footprint_origin(g.bu, W, G) - x0, G);   // in [0, 2T)
-        const int oy = mod_pos(footprint_origin(g.bv, W, G) - y0, G);
+        const int ox = wrap_g(footprint_origin(g.bu, W, G) - x0, G);   // in [0, 2T)
+        const int oy = wrap_g(footprint_origin(g.bv, W, G) - y0, G);
         float wy[W];
 #pragma unroll
-        for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbc, kbS, hw);
+        for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbt, kbS, hw);
         const float2* src = tile + ox * P + oy;
         float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
         for (int al = 0; al < W; ++al) {
-            const float wx = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbc, kbS, hw);
+            const float wx = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbt, kbS, hw);
             float2 racc = make_float2(0.f, 0.f);
 #pragma unroll
             for (int gm = 0; gm < W; ++gm) {
@@ -411,24 +427,32 @@ __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, 
 
 // ---------------------------------------------------------------- A2
 // Deterministic binned spreading. One workgroup per work item: a slice of
-// at most A2_MAX_VISITS visits of one output tile's visit list, which is the
+// at most A2_CHUNK visits of one output tile's visit list, which is the
 // concatenation of the diagonal neighbour bin's class 2, the v-neighbour's
 // classes 2-3, the u-neighbour's classes 1-2 and the whole own bin -- exactly
-// the samples whose footprint reaches the tile.
+// the samples whose footprint reaches the tile. Each thread takes up to
+// A2_VPT visits and adds their W x W footprints into a halo'd LDS tile.
 //
-// Every thread prepares up to A2_VPT visits (W x-weights, W values Y*wy).
-// Contributions are accumulated as 64-bit fixed-point integers in a halo'd
-// LDS tile with integer atomic adds: integer addition is exact and
-// commutative, so the sums do not depend on the order in which lanes and
-// waves arrive, and the result is bitwise reproducible without any floating-
-// point atomics. Each contribution is the exact product of x = round(wx*2^24)
-// (wx in [0, 1]) and y = round(Y*wy*2^s) (|y| < 2^31); s is chosen per work
-// item from the item's largest |Y*wy| so that count * 2^24 * max|y| < 2^62,
-// which bounds every partial sum. The relative rounding of y (2^-28 or finer
-// of the item's largest value) is far below float32 resolution of the sums.
-constexpr int A2_NT = 256;
-constexpr int A2_VPT = 4;
-constexpr int A2_MAX_VISITS = A2_NT * A2_VPT;
+// The tile is accumulated in fixed point with 64-bit integer atomic adds, the
+// real and imaginary parts packed into one word: a contribution (c_re, c_im)
+// of two int32 adds c_re + 2^32 c_im (mod 2^64). Integer addition is exact,
+// commutative and associative, so the word ends as S_re + 2^32 S_im (mod
+// 2^64) whatever the order in which lanes and waves arrive, and S_re, S_im are
+// recovered exactly when both lie in [-2^31, 2^31): the result is bitwise
+// reproducible without floating-point atomics, and one atomic carries both
+// parts. c = round(wx * Y * wy * 2^s), with the item's scale s chosen from
+// its largest |Y * wy| so that count * max|c| < 2^31 bounds every final sum;
+// each contribution is then rounded to 2^-22 (count 512) of the item's
+// largest one, about the resolution of float32.
+#ifndef RN_A2_NT
+#define RN_A2_NT 256
+#endif
+#ifndef RN_A2_CHUNK
+#define RN_A2_CHUNK 512
+#endif
+constexpr int A2_NT = RN_A2_NT;
+constexpr int A2_CHUNK = RN_A2_CHUNK;
+constexpr int A2_VPT = (A2_CHUNK + A2_NT - 1) / A2_NT;
 
 template <int W, int T>
 __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict__ items,
@@ -438,7 +462,9 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
                                                     float2* __restrict__ grid, float2* __restrict__ partials,
                                                     int G, int ND, int n_views) {
     constexpr int P = T + 2 * (W - 1);   // accumulator side: local [-(W-1), T+W-1)
-    __shared__ unsigned long long acc[2 * P * P];   // (re, im) per point
+    constexpr int NKB = (W / 2) * KB_S;
+    __shared__ unsigned long long acc[P * P];
+    __shared__ float4 kbt[NKB];
     __shared__ float wmax[A2_NT / 64];
     const int tid = threadIdx.x;
     const TileItem it = items[blockIdx.x];
@@ -447,7 +473,9 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
     const int HQ = ND / 2 + 1;
     const float hw = 0.5f * (float)W;
 
-    for (int e = tid; e < 2 * P * P; e += A2_NT) acc[e] = 0ull;
+    for (int e = tid; e < P * P; e += A2_NT) acc[e] = 0ull;
+    for (int e = tid; e < NKB; e += A2_NT) kbt[e] = kbc[e];
+    __syncthreads();
 
     const int xl = (it.cx + ntl - 1) % ntl, yu = (it.cy + ntl - 1) % ntl;
     const int b_ul = yu * ntl + xl, b_u = yu * ntl + it.cx, b_l = it.cy * ntl + xl, b_o = it.cy * ntl + it.cx;
@@ -489,10 +517,10 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
             base[k] = (ox + W - 1) * P + (oy + W - 1);
 #pragma unroll
             for (int al = 0; al < W; ++al)
-                wx[k][al] = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbc, kbS, hw);
+                wx[k][al] = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbt, kbS, hw);
 #pragma unroll
             for (int gm = 0; gm < W; ++gm) {
-                const float wy = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbc, kbS, hw);
+                const float wy = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbt, kbS, hw);
                 ywy[k][gm] = make_float2(Y.x * wy, Y.y * wy);
                 mx_abs = fmaxf(mx_abs, fmaxf(fabsf(ywy[k][gm].x), fabsf(ywy[k][gm].y)));
             }
@@ -506,27 +534,24 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
     float m = wmax[0];
 #pragma unroll
     for (int w = 1; w < A2_NT / 64; ++w) m = fmaxf(m, wmax[w]);
-    // scale 2^s: max|y| < 2^31 and count * 2^24 * 2^s * max < 2^62
+    // scale 2^s: m * 2^s < 2^(30 - lc), so count * max|c| < 2^30 + count/2 < 2^31
     int e = 0;
     (void)frexpf(m, &e);                       // m < 2^e
     int lc = 0;
     while ((1 << lc) < it.count) ++lc;         // count <= 2^lc
-    const int s = min(31, 38 - lc) - e;
+    const int s = 30 - lc - e;
 #pragma unroll
     for (int k = 0; k < A2_VPT; ++k) {
         if (base[k] < 0) continue;
-        int xi[W];
-#pragma unroll
-        for (int al = 0; al < W; ++al) xi[al] = __float2int_rn(wx[k][al] * 16777216.0f);
 #pragma unroll
         for (int gm = 0; gm < W; ++gm) {
-            const long long yr = __float2int_rn(ldexpf(ywy[k][gm].x, s));
-            const long long yi = __float2int_rn(ldexpf(ywy[k][gm].y, s));
+            const float yr = ldexpf(ywy[k][gm].x, s), yi = ldexpf(ywy[k][gm].y, s);
 #pragma unroll
             for (int al = 0; al < W; ++al) {
-                const int idx = 2 * (base[k] + al * P + gm);
-                atomicAdd(&acc[idx], (unsigned long long)(yr * xi[al]));
-                atomicAdd(&acc[idx + 1], (unsigned long long)(yi * xi[al]));
+                const long long cr = __float2int_rn(wx[k][al] * yr);
+                const long long ci = __float2int_rn(wx[k][al] * yi);
+                atomicAdd(&acc[base[k] + al * P + gm],
+                          (unsigned long long)cr + ((unsigned long long)ci << 32));
             }
         }
     }
@@ -534,14 +559,14 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
     // write out: local (lx, ly) -> mx = (x0 + lx - G/2) mod G, my = (y0 + ly - G/2) mod G
     const int xvalid = (it.cx == 0) ? 1 : T;   // tile column 0 holds only mx = G/2
     const int my0 = mod_pos(y0 - G / 2, G);
-    const int sh = -(s + 24);
     for (int e2 = tid; e2 < xvalid * T; e2 += A2_NT) {
         const int lx = e2 / T, ly = e2 - lx * T;
-        const int idx = 2 * ((lx + W - 1) * P + (ly + W - 1));
-        const float2 val = make_float2((float)ldexp((double)(long long)acc[idx], sh),
-                                       (float)ldexp((double)(long long)acc[idx + 1], sh));
+        const unsigned long long w = acc[(lx + W - 1) * P + (ly + W - 1)];
+        const int sre = (int)(unsigned int)(w & 0xffffffffull);
+        const int sim = (int)((long long)(w - (unsigned long long)(long long)sre) >> 32);
+        const float2 val = make_float2((float)ldexp((double)sre, -s), (float)ldexp((double)sim, -s));
         if (it.slot < 0) {
-            const int mx = mod_pos(x0 + lx - G / 2, G);
+            const int mx = wrap_g(x0 + lx - G / 2, G);
             grid[(size_t)mx * G + my0 + ly] = val;
         } else {
             partials[(size_t)it.slot * T * T + e2] = val;
@@ -563,11 +588,24 @@ __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__
     const int xvalid = (sp.cx == 0) ? 1 : T;
     const int x0 = sp.cx * T, y0 = sp.cy * T;
     const int my0 = mod_pos(y0 - G / 2, G);
+    const float2* src = partials + (size_t)sp.first_slot * T * T;
     for (int e = threadIdx.x; e < xvalid * T; e += 256) {
-        float2 s = partials[(size_t)sp.first_slot * T * T + e];
-        for (int k = 1; k < sp.nslots; ++k) s = cadd(s, partials[(size_t)(sp.first_slot + k) * T * T + e]);
+        // slots are added in order; the loads of eight slots are issued together
+        float2 s = make_float2(0.f, 0.f);
+        int k = 0;
+        for (; k + 8 <= sp.nslots; k += 8) {
+            float2 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(k + j) * T * T + e];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s = (k + j == 0) ? v[j] : cadd(s, v[j]);
+        }
+        for (; k < sp.nslots; ++k) {
+            const float2 v = src[(size_t)k * T * T + e];
+            s = (k == 0) ? v : cadd(s, v);
+        }
         const int lx = e / T, ly = e - lx * T;
-        const int mx = mod_pos(x0 + lx - G / 2, G);
+        const int mx = wrap_g(x0 + lx - G / 2, G);
         grid[(size_t)mx * G + my0 + ly] = s;
     }
 }
