@@ -28,8 +28,7 @@ template <int W, int T>
 static hipError_t launch_a2_wt(const Plan& p, hipStream_t st) {
     if (p.n_items == 0) return hipSuccess;
     hipLaunchKernelGGL((k_a2_spread<W, T>), dim3(p.n_items), dim3(A2_NT), 0, st, p.items, p.offs4,
-                       p.perm, p.Yh, p.cs, p.kbc, p.kbS, p.grid, p.partials, p.G, p.n_det,
-                       p.n_views);
+                       p.recs, p.Yh, p.kbc, p.kbS, p.grid, p.partials, p.G);
     return hipGetLastError();
 }
 

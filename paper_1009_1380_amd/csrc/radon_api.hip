@@ -40,7 +40,7 @@ radon_status_t ok() {
 // partial tiles summed in a fixed order.
 constexpr int kA2Chunk = rn::A2_CHUNK;
 // Samples per forward interpolation work item.
-constexpr int kF3Chunk = 2048;
+constexpr int kF3Chunk = rn::F3_CHUNK;
 // Cubic Kaiser-Bessel pieces per unit of t (a power of two).
 constexpr int kKbS = rn::KB_S;
 
@@ -256,6 +256,8 @@ radon_status_t sort_samples(Plan& p, std::vector<int>& offsets_host) {
     }
     hipLaunchKernelGGL(rn::k_bin_offsets, dim3((n_keys + 1 + 255) / 256), dim3(256), 0, 0, k0, total,
                        p.offs4, n_keys);
+    hipLaunchKernelGGL(rn::k_sample_recs, dim3((total + 255) / 256), dim3(256), 0, 0, v0, p.cs, p.recs, total,
+                       p.n_views, p.n_det, p.G, p.W, p.T);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpy(p.perm, v0, sizeof(int) * total, hipMemcpyDeviceToDevice);
     offsets_host.assign(n_keys + 1, 0);
@@ -327,6 +329,14 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
                      [](const rn::F3Item& a, const rn::F3Item& b) { return a.count > b.count; });
     p.n_items = (int)items.size();
     p.n_fitems = (int)fitems.size();
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p.device) != hipSuccess || cus < 1) {
+            (void)hipGetLastError();
+            cus = 1;
+        }
+        p.f3_grid = std::max(1, std::min(p.n_fitems, rn::f3_blocks_per_cu(p) * cus));
+    }
     p.n_splits = (int)splits.size();
     p.n_slots = slots;
     radon_status_t s;
@@ -387,6 +397,7 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
     if ((s = dev_alloc(p, &p.kbc, kbc.size())) || (s = upload(p.kbc, kbc))) return s;
     if ((s = dev_alloc(p, &p.fbpw, n_det / 2 + 1)) || (s = upload(p.fbpw, ramp_weights(n_views, n_det)))) return s;
     if ((s = dev_alloc(p, &p.perm, (size_t)p.n_samples))) return s;
+    if ((s = dev_alloc(p, &p.recs, (size_t)p.n_samples))) return s;
     if ((s = dev_alloc(p, &p.offs4, (size_t)4 * p.n_bins + 1))) return s;
     std::vector<int> offs;
     if ((s = sort_samples(p, offs))) return s;
@@ -455,7 +466,7 @@ radon_status_t radon_plan(radon_plan_t* out, int n, const double* angles, int n_
     if (!is_supported_length(n)) return fail(RADON_ERR_UNSUPPORTED, "n=%d is not a supported FFT length", n);
     if (!is_supported_length(n_det))
         return fail(RADON_ERR_UNSUPPORTED, "n_det=%d is not a supported FFT length", n_det);
-    if ((int64_t)n_views * n_det + n_views >= (int64_t)1 << 30)
+    if ((int64_t)n_views * n_det + n_views >= (int64_t)1 << 30 || (int64_t)n_views * (n_det / 2 + 1) >= (int64_t)1 << 29)
         return fail(RADON_ERR_UNSUPPORTED, "too many samples");
 
     radon_plan_s* plan = new (std::nothrow) radon_plan_s();

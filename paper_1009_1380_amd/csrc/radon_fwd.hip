@@ -44,9 +44,38 @@ hipError_t launch_f2(const Plan& p, hipStream_t st) {
 template <int W, int T>
 static hipError_t launch_f3_wt(const Plan& p, hipStream_t st) {
     if (p.n_fitems == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_f3_tiles<W, T, 512>), dim3(p.n_fitems), dim3(512), 0, st, p.fitems, p.offs4, p.perm,
-                       p.grid, p.cs, p.kbc, p.kbS, p.Xr, p.G, p.n_det, p.n_views);
+    hipLaunchKernelGGL((k_f3_tiles<W, T, 512>), dim3(p.f3_grid), dim3(512), 0, st, p.fitems, p.n_fitems, p.offs4,
+                       p.recs, p.grid, p.kbc, p.kbS, p.Xr, p.G);
     return hipGetLastError();
+}
+
+template <int W, int T>
+static int f3_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_f3_tiles<W, T, 512>, 512, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+template <int W>
+static int f3_occupancy_w(int T) {
+    switch (T) {
+        case 8: return f3_occupancy<W, 8>();
+        case 16: return f3_occupancy<W, 16>();
+        case 32: return f3_occupancy<W, 32>();
+        default: return 1;
+    }
+}
+
+int f3_blocks_per_cu(const Plan& p) {
+    switch (p.W) {
+        case 4: return f3_occupancy_w<4>(p.T);
+        case 6: return f3_occupancy_w<6>(p.T);
+        case 8: return f3_occupancy_w<8>(p.T);
+        default: return 1;
+    }
 }
 
 template <int W>

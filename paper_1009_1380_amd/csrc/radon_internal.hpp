@@ -43,6 +43,7 @@ struct Plan {
     int n_bins = 0;                     // tiles; the sort has 4 edge classes per tile
     int n_items = 0, n_slots = 0, n_splits = 0;   // spreading work
     int n_fitems = 0;                   // forward interpolation work
+    int f3_grid = 0;                    // workgroups of the persistent forward interpolation
     float kbS = 0;                      // cubic pieces per unit of t
 
     // device tables
@@ -59,6 +60,7 @@ struct Plan {
     float2* Yh = nullptr;        // n_views x (N/2+1) complex64 (adjoint ray spectra)
     float2* Xr = nullptr;        // n_views x (N/2+1) complex64 (forward polar samples)
     int* perm = nullptr;         // sorted sample ids
+    SampleRec* recs = nullptr;   // per sorted sample: origin, fractions, spectrum index, flags
     int* offs4 = nullptr;        // 4 * n_bins + 1 class starts
     F3Item* fitems = nullptr;
     TileItem* items = nullptr;
@@ -78,6 +80,7 @@ struct Plan {
 hipError_t launch_f1(const Plan& p, const float* img, hipStream_t st);
 hipError_t launch_f2(const Plan& p, hipStream_t st);
 hipError_t launch_f3(const Plan& p, hipStream_t st);
+int f3_blocks_per_cu(const Plan& p);   // resident forward-interpolation workgroups per CU
 hipError_t launch_f4(const Plan& p, float* sino, hipStream_t st);
 hipError_t launch_a1(const Plan& p, const float* sino, bool filtered, hipStream_t st);
 hipError_t launch_a2(const Plan& p, hipStream_t st);

@@ -42,7 +42,21 @@ namespace rn {
 // pieces per unit of t (c.x + c.y f + c.z f^2 + c.w f^3 on piece floor(t S),
 // f = frac(t S)); strict support: 0 for t >= W/2. S is a power of two, so
 // t * S is exact and the piece index stays below (W/2) S.
+// Branch-free: the piece index is clamped into the table and the result
+// selected to 0 outside the support, so all of a footprint's table reads can
+// be issued together.
 __device__ __forceinline__ float kb_weight(float t, const float4* __restrict__ tab, float S, float half_w) {
+    const float x = fminf(t, half_w) * S;
+    const int i = min((int)x, (int)(half_w * S) - 1);
+    const float f = x - (float)i;
+    const float4 c = tab[i];
+    const float w = fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
+    return t < half_w ? w : 0.0f;
+}
+
+// The same weight with an early exit outside the support (fewer registers
+// when the caller keeps many weights live).
+__device__ __forceinline__ float kb_weight_br(float t, const float4* __restrict__ tab, float S, float half_w) {
     if (!(t < half_w)) return 0.0f;
     const float x = t * S;
     const int i = (int)x;
@@ -50,6 +64,9 @@ __device__ __forceinline__ float kb_weight(float t, const float4* __restrict__ t
     const float4 c = tab[i];
     return fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
 }
+#ifndef RN_A2_KB
+#define RN_A2_KB kb_weight_br
+#endif
 
 struct SampleGeom {
     int bu, bv;      // floor(u), floor(v)
@@ -246,6 +263,35 @@ struct TileItem {
     int pad0, pad1, pad2;
 };
 
+// Per-sample record in sorted order, built once per plan so that the
+// gridding kernels need no geometry of their own:
+//   org   footprint origin, o_u | o_v << 16 (centred grid coordinates)
+//   fu,fv u - floor(u), v - floor(v) (float32, as sample_geom gives them)
+//   info  bits 0..28: index a*(N/2+1) + t of the sample's ray-spectrum entry
+//         (t = |q|, or N/2 for both Nyquist samples); bit 29: q in (-N/2, 0)
+//         (the entry is the conjugate); bit 30: mirrored Nyquist sample;
+//         bit 31: the forward interpolation evaluates this sample (one member
+//         of each conjugate pair, chosen by the rule of F3 below).
+struct SampleRec {
+    int org;
+    float fu, fv;
+    int info;
+};
+constexpr int REC_IDX_MASK = (1 << 29) - 1;
+constexpr int REC_CONJ = 1 << 29;
+constexpr int REC_MIRROR = 1 << 30;
+constexpr unsigned REC_F3 = 1u << 31;
+
+__device__ __forceinline__ SampleRec load_rec(const SampleRec* __restrict__ recs, int pos) {
+    const int4 r = reinterpret_cast<const int4*>(recs)[pos];
+    SampleRec o;
+    o.org = r.x;
+    o.fu = __int_as_float(r.y);
+    o.fv = __int_as_float(r.z);
+    o.info = r.w;
+    return o;
+}
+
 // ---------------------------------------------------------------- F3
 // Kaiser-Bessel interpolation of the polar samples from the half-plane grid.
 // One workgroup per super-tile of 2 x 2 bins (the bins of tile columns cx and
@@ -264,91 +310,85 @@ struct F3Item {
     int pad0, pad1, pad2;
 };
 
+// Persistent: workgroup b takes items b, b + gridDim.x, ... (the grid is the
+// number of workgroups that fit on the device at once). Sample geometry comes
+// precomputed from the plan's per-sample records.
+constexpr int F3_CHUNK = 2048;   // samples per work item
+
 template <int W, int T, int NT>
-__global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ items, const int* __restrict__ offs4,
-                                                const int* __restrict__ perm, const float2* __restrict__ grid,
-                                                const double2* __restrict__ cs, const float4* __restrict__ kbc,
-                                                float kbS, float2* __restrict__ Xr, int G, int ND, int n_views) {
+__global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ items, int n_items,
+                                                const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
+                                                const float2* __restrict__ grid, const float4* __restrict__ kbc,
+                                                float kbS, float2* __restrict__ Xr, int G) {
     constexpr int P = 2 * T + W - 1;
+    constexpr int PP = P * P;
+    constexpr int PE = (PP + NT - 1) / NT;            // staged points per thread
     constexpr int NKB = (W / 2) * KB_S;
-    __shared__ float2 tile[P * P];   // [lx][ly], lx along u (mx), ly along v (my)
+    __shared__ float2 tile[PP];   // [lx][ly], lx along u (mx), ly along v (my)
     __shared__ float4 kbt[NKB];
     const int tid = threadIdx.x;
-    const F3Item it = items[blockIdx.x];
-    const int x0 = it.cx * T, y0 = it.cy * T;
     const int ntl = G / T;
-    const int M = n_views * ND;
-    const int HQ = ND / 2 + 1;
     const float hw = 0.5f * (float)W;
-    // sample ranges of the (up to) four bins, in the order (x0,y0) (x1,y0) (x0,y1) (x1,y1)
-    const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
-    const int b0 = it.cy * ntl + it.cx, b1 = it.cy * ntl + cx1, b2 = cy1 * ntl + it.cx, b3 = cy1 * ntl + cx1;
-    const int s0 = offs4[4 * b0], n0 = offs4[4 * b0 + 4] - s0;
-    const int s1 = offs4[4 * b1], n1 = (it.nbx > 1) ? offs4[4 * b1 + 4] - s1 : 0;
-    const int s2 = offs4[4 * b2], n2 = offs4[4 * b2 + 4] - s2;
-    const int s3 = offs4[4 * b3];
 
-    // stage the kernel table and the super-tile
     for (int e = tid; e < NKB; e += NT) kbt[e] = kbc[e];
-    for (int e = tid; e < P * P; e += NT) {
-        const int lx = e / P, ly = e - lx * P;
-        int mx = wrap_g(x0 + lx, G) - G / 2;        // in [-G/2, G/2)
-        const int my = wrap_g(y0 + ly, G) - G / 2;
-        if (mx == -G / 2) mx = G / 2;
-        float2 val;
-        if (mx >= 0) {
-            val = grid[(size_t)mx * G + wrap_g(my, G)];
-        } else {
-            val = cconj(grid[(size_t)(-mx) * G + wrap_g(-my, G)]);
-        }
-        tile[e] = val;
-    }
-    __syncthreads();
-    for (int k = tid; k < it.count; k += NT) {
-        int u = it.start + k, pos;
-        if (u < n0) pos = s0 + u;
-        else if ((u -= n0) < n1) pos = s1 + u;
-        else if ((u -= n1) < n2) pos = s2 + u;
-        else pos = s3 + (u - n2);
-        const int v = perm[pos];
-        int a, q;
-        decode_sample(v, M, ND, a, q);
-        const double2 csa = cs[a];
-        bool conj_out = false;
-        int t;
-        if (q == -ND / 2) { t = ND / 2; }
-        else if (q >= 0 && q < ND / 2) { t = q; }
-        else {
-            // a mirror: evaluated only if its canonical partner's origin tile
-            // is not a forward column
-            const int qc = (q == ND / 2) ? -ND / 2 : -q;
-            const SampleGeom gc = sample_geom(csa.x, csa.y, qc, G, ND);
-            if (forward_column(footprint_origin(gc.bu, W, G) / T, ntl)) continue;
-            t = (q == ND / 2) ? ND / 2 : -q;
-            conj_out = true;
-        }
-        const SampleGeom g = sample_geom(csa.x, csa.y, q, G, ND);
-        const int ox = wrap_g(footprint_origin(g.bu, W, G) - x0, G);   // in [0, 2T)
-        const int oy = wrap_g(footprint_origin(g.bv, W, G) - y0, G);
-        float wy[W];
+
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+        const F3Item it = items[i];
+        const int x0 = it.cx * T, y0 = it.cy * T;
+        __syncthreads();   // the previous item's samples are done with the tile
+        // stage the region; points with mx < 0 hold the conjugate of their mirror
 #pragma unroll
-        for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbt, kbS, hw);
-        const float2* src = tile + ox * P + oy;
-        float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int al = 0; al < W; ++al) {
-            const float wx = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbt, kbS, hw);
-            float2 racc = make_float2(0.f, 0.f);
-#pragma unroll
-            for (int gm = 0; gm < W; ++gm) {
-                const float2 val = src[al * P + gm];
-                racc.x = fmaf(wy[gm], val.x, racc.x);
-                racc.y = fmaf(wy[gm], val.y, racc.y);
+        for (int k = 0; k < PE; ++k) {
+            const int e = tid + k * NT;
+            if (e < PP) {
+                const int lx = e / P, ly = e - lx * P;
+                int mx = wrap_g(x0 + lx, G) - G / 2;        // in [-G/2, G/2)
+                int my = wrap_g(y0 + ly, G) - G / 2;
+                if (mx == -G / 2) mx = G / 2;
+                const bool mirror = mx < 0;
+                if (mirror) { mx = -mx; my = -my; }
+                const float2 g = grid[(size_t)mx * G + wrap_g(my, G)];
+                tile[e] = make_float2(g.x, mirror ? -g.y : g.y);
             }
-            acc.x = fmaf(wx, racc.x, acc.x);
-            acc.y = fmaf(wx, racc.y, acc.y);
         }
-        Xr[(size_t)a * HQ + t] = conj_out ? cconj(acc) : acc;
+        __syncthreads();
+        const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
+        const int b0 = it.cy * ntl + it.cx, b1 = it.cy * ntl + cx1, b2 = cy1 * ntl + it.cx, b3 = cy1 * ntl + cx1;
+        const int s0 = offs4[4 * b0], n0 = offs4[4 * b0 + 4] - s0;
+        const int s1 = offs4[4 * b1], n1 = (it.nbx > 1) ? offs4[4 * b1 + 4] - s1 : 0;
+        const int s2 = offs4[4 * b2], n2 = offs4[4 * b2 + 4] - s2;
+        const int s3 = offs4[4 * b3];
+        for (int k = tid; k < it.count; k += NT) {
+            int u = it.start + k, pos;
+            if (u < n0) pos = s0 + u;
+            else if ((u -= n0) < n1) pos = s1 + u;
+            else if ((u -= n1) < n2) pos = s2 + u;
+            else pos = s3 + (u - n2);
+            const SampleRec r = load_rec(recs, pos);
+            if (!((unsigned)r.info & REC_F3)) continue;
+            const int ox = wrap_g((r.org & 0xffff) - x0, G);   // in [0, 2T)
+            const int oy = wrap_g((r.org >> 16) - y0, G);
+            float wy[W];
+#pragma unroll
+            for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(fabsf(r.fv + (float)(W / 2 - 1 - gm)), kbt, kbS, hw);
+            const float2* src = tile + ox * P + oy;
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int al = 0; al < W; ++al) {
+                const float wx = kb_weight(fabsf(r.fu + (float)(W / 2 - 1 - al)), kbt, kbS, hw);
+                float2 racc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int gm = 0; gm < W; ++gm) {
+                    const float2 val = src[al * P + gm];
+                    racc.x = fmaf(wy[gm], val.x, racc.x);
+                    racc.y = fmaf(wy[gm], val.y, racc.y);
+                }
+                acc.x = fmaf(wx, racc.x, acc.x);
+                acc.y = fmaf(wx, racc.y, acc.y);
+            }
+            const bool cj = (r.info & (REC_CONJ | REC_MIRROR)) != 0;
+            Xr[r.info & REC_IDX_MASK] = cj ? cconj(acc) : acc;
+        }
     }
 }
 
@@ -456,11 +496,12 @@ constexpr int A2_VPT = (A2_CHUNK + A2_NT - 1) / A2_NT;
 
 template <int W, int T>
 __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict__ items,
-                                                    const int* __restrict__ offs4, const int* __restrict__ perm,
-                                                    const float2* __restrict__ Yh, const double2* __restrict__ cs,
+                                                    const int* __restrict__ offs4,
+                                                    const SampleRec* __restrict__ recs,
+                                                    const float2* __restrict__ Yh,
                                                     const float4* __restrict__ kbc, float kbS,
                                                     float2* __restrict__ grid, float2* __restrict__ partials,
-                                                    int G, int ND, int n_views) {
+                                                    int G) {
     constexpr int P = T + 2 * (W - 1);   // accumulator side: local [-(W-1), T+W-1)
     constexpr int NKB = (W / 2) * KB_S;
     __shared__ unsigned long long acc[P * P];
@@ -469,8 +510,6 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
     const int tid = threadIdx.x;
     const TileItem it = items[blockIdx.x];
     const int ntl = G / T;
-    const int M = n_views * ND;
-    const int HQ = ND / 2 + 1;
     const float hw = 0.5f * (float)W;
 
     for (int e = tid; e < P * P; e += A2_NT) acc[e] = 0ull;
@@ -499,17 +538,11 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
             else if ((u -= n0) < n1) pos = s1 + u;
             else if ((u -= n1) < n2) pos = s2 + u;
             else pos = s3 + (u - n2);
-            const int v = perm[pos];
-            int a, q;
-            decode_sample(v, M, ND, a, q);
-            float2 Y;
-            if (q >= 0 && q < ND / 2) Y = Yh[(size_t)a * HQ + q];
-            else if (q < 0 && q > -ND / 2) Y = cconj(Yh[(size_t)a * HQ - q]);
-            else Y = Yh[(size_t)a * HQ + ND / 2];
-            const double2 csa = cs[a];
-            const SampleGeom g = sample_geom(csa.x, csa.y, q, G, ND);
-            int ox = footprint_origin(g.bu, W, G) - x0;
-            int oy = footprint_origin(g.bv, W, G) - y0;
+            const SampleRec r = load_rec(recs, pos);
+            float2 Y = Yh[r.info & REC_IDX_MASK];
+            if (r.info & REC_CONJ) Y = cconj(Y);
+            int ox = (r.org & 0xffff) - x0;
+            int oy = (r.org >> 16) - y0;
             if (ox >= G / 2) ox -= G;
             if (ox < -G / 2) ox += G;
             if (oy >= G / 2) oy -= G;
@@ -517,10 +550,10 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
             base[k] = (ox + W - 1) * P + (oy + W - 1);
 #pragma unroll
             for (int al = 0; al < W; ++al)
-                wx[k][al] = kb_weight(fabsf(g.fu + (float)(W / 2 - 1 - al)), kbt, kbS, hw);
+                wx[k][al] = RN_A2_KB(fabsf(r.fu + (float)(W / 2 - 1 - al)), kbt, kbS, hw);
 #pragma unroll
             for (int gm = 0; gm < W; ++gm) {
-                const float wy = kb_weight(fabsf(g.fv + (float)(W / 2 - 1 - gm)), kbt, kbS, hw);
+                const float wy = RN_A2_KB(fabsf(r.fv + (float)(W / 2 - 1 - gm)), kbt, kbS, hw);
                 ywy[k][gm] = make_float2(Y.x * wy, Y.y * wy);
                 mx_abs = fmaxf(mx_abs, fmaxf(fabsf(ywy[k][gm].x), fabsf(ywy[k][gm].y)));
             }

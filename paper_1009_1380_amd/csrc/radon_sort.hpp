@@ -45,6 +45,44 @@ __global__ __launch_bounds__(256) void k_sample_keys(const double2* __restrict__
     ids[v] = v;
 }
 
+// Records of the sorted samples (see SampleRec): geometry, ray-spectrum index
+// and the forward-evaluation flag, from the same float64 geometry as the keys.
+__global__ __launch_bounds__(256) void k_sample_recs(const int* __restrict__ perm, const double2* __restrict__ cs,
+                                                    SampleRec* __restrict__ recs, int total, int n_views, int ND,
+                                                    int G, int W, int T) {
+    const int pos = blockIdx.x * 256 + threadIdx.x;
+    if (pos >= total) return;
+    const int M = n_views * ND;
+    const int HQ = ND / 2 + 1;
+    const int ntl = G / T;
+    int a, q;
+    decode_sample(perm[pos], M, ND, a, q);
+    const double2 c = cs[a];
+    const SampleGeom g = sample_geom(c.x, c.y, q, G, ND);
+    int idx, flags = 0;
+    bool eval = true;
+    if (q >= 0 && q < ND / 2) {
+        idx = a * HQ + q;
+    } else if (q == -ND / 2) {
+        idx = a * HQ + ND / 2;
+    } else {
+        // q in (-N/2, 0), or the mirrored Nyquist sample (q = +N/2): the forward
+        // evaluates it only if its partner's origin is not in a forward column
+        const bool mirror = (q == ND / 2);
+        const int qc = mirror ? -ND / 2 : -q;
+        const SampleGeom gc = sample_geom(c.x, c.y, qc, G, ND);
+        eval = !forward_column(footprint_origin(gc.bu, W, G) / T, ntl);
+        idx = mirror ? a * HQ + ND / 2 : a * HQ - q;
+        flags = mirror ? REC_MIRROR : REC_CONJ;
+    }
+    int4 r;
+    r.x = footprint_origin(g.bu, W, G) | (footprint_origin(g.bv, W, G) << 16);
+    r.y = __float_as_int(g.fu);
+    r.z = __float_as_int(g.fv);
+    r.w = (int)((unsigned)idx | (unsigned)flags | (eval ? REC_F3 : 0u));
+    reinterpret_cast<int4*>(recs)[pos] = r;
+}
+
 // Per-block digit counts, stored digit-major: hist[d * nblocks + b].
 __global__ __launch_bounds__(SORT_NT) void k_sort_hist(const int* __restrict__ keys, int n, int shift,
                                                       int* __restrict__ hist, int nblocks) {
