@@ -57,15 +57,20 @@ def kernel_bytes(n: int, n_views: int, n_det: int):
     }
 
 
+# the files that define the path's kernels and their launch shapes
+KERNEL_SOURCES = ("fft_lds.hpp", "radon_kernels.hpp", "radon_sort.hpp", "radon_fwd.hip", "radon_adj.hip")
+
+
 def source_hash() -> str:
+    """Hash of the kernel sources; counter-derived traffic is reported only
+    while the kernels are the ones the counters were taken on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1009_1380_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
-    return h.hexdigest()[:16]
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def load_traffic(kernel: str, n_launch_bytes: int):
