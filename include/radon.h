@@ -76,6 +76,46 @@ typedef enum {
 radon_status_t radon_plan(radon_plan_t* out, int n, const double* angles, int n_views,
                           int n_det, double sigma, int W);
 
+/*
+ * Work decomposition of a plan (section "fast radon transform", paragraph 4:
+ * the bins that balance the gridding work, read as uniform tiles):
+ *   tile      side T of the square bins: 8, 16 or 32 with T dividing G/2 and
+ *             T >= W; 0 = the largest that fits.
+ *   a2_chunk  most visits in one spreading work item, 64..512; 0 = 512.
+ *   f3_chunk  most samples in one forward-interpolation work item,
+ *             256..65536; 0 = 2048.
+ * Results do not depend on the choice beyond float32 rounding.
+ */
+typedef struct {
+    int tile;
+    int a2_chunk;
+    int f3_chunk;
+} radon_tuning;
+
+/* radon_plan with an explicit work decomposition (tuning may be NULL: the
+ * defaults). Out-of-range tuning values return RADON_ERR_INVALID; a tile that
+ * does not fit G returns RADON_ERR_UNSUPPORTED. */
+radon_status_t radon_plan_tuned(radon_plan_t* out, int n, const double* angles, int n_views,
+                                int n_det, double sigma, int W, const radon_tuning* tuning);
+
+/* The work decomposition a plan uses (defaults resolved). */
+radon_status_t radon_plan_tuning(radon_plan_t plan, radon_tuning* out);
+
+/*
+ * Autotuner: for the given geometry, time `repeats` forward + adjoint pairs
+ * (after one untimed pair) of candidate decompositions on `stream`, by
+ * coordinate search from the defaults: the tile size over {8, 16, 32} (those
+ * that fit), then a2_chunk over {256, 512}, then f3_chunk over {1024, 2048,
+ * 4096}, each step keeping the fastest so far. Returns the fastest in *best
+ * with its time per pair in *best_ms; *default_ms (may be NULL) gets the time
+ * of the default decomposition. Inputs are generated on the device; the
+ * plans and buffers are released before returning. Synchronises the stream.
+ * Errors in the geometry are reported as by radon_plan.
+ */
+radon_status_t radon_autotune(int n, const double* angles, int n_views, int n_det, double sigma, int W,
+                              int repeats, radon_tuning* best, double* best_ms, double* default_ms,
+                              void* stream);
+
 /* Forward Radon transform: img_dev (n*n float32) -> sino_dev (n_views*n_det float32). */
 radon_status_t radon_forward(radon_plan_t plan, const float* img_dev, float* sino_dev,
                              void* stream);
@@ -101,6 +141,27 @@ radon_status_t radon_forward_batched(radon_plan_t plan, int batch, const float* 
                                      float* sinos_dev, void* stream);
 radon_status_t radon_adjoint_batched(radon_plan_t plan, int batch, const float* sinos_dev,
                                      float* imgs_dev, void* stream);
+
+/*
+ * Batches of uneven slices: `count` plans of any sizes (distinct plan objects,
+ * each used by this batch only while it runs) applied together. The first
+ * call for a given set of device pointers records every slice's kernels into
+ * one HIP graph, the slices dealt round-robin over `n_branches` independent
+ * branches (1..16) so that small slices run side by side; later calls with
+ * the same pointers replay the graph with a single launch on `stream`. New
+ * pointers record a new graph. imgs_dev[i] is plan i's n*n image,
+ * sinos_dev[i] its n_views*n_det sinogram. Profiling must be off on every
+ * plan. The batch keeps the plan handles: destroy it before them.
+ */
+typedef struct radon_batch_s* radon_batch_t;
+radon_status_t radon_batch_create(radon_batch_t* out, int count, const radon_plan_t* plans, int n_branches);
+radon_status_t radon_batch_forward(radon_batch_t batch, const float* const* imgs_dev, float* const* sinos_dev,
+                                   void* stream);
+radon_status_t radon_batch_adjoint(radon_batch_t batch, const float* const* sinos_dev, float* const* imgs_dev,
+                                   void* stream);
+/* Number of graphs recorded so far (a test hook: replays do not add one). */
+int radon_batch_graphs_recorded(radon_batch_t batch);
+void radon_batch_destroy(radon_batch_t batch);   /* NULL-safe */
 
 /*
  * Test hook: copy the plan's stable sample sort to host memory. The sorted

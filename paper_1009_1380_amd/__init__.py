@@ -1,5 +1,6 @@
 """MI355X (gfx950) Fourier-slice Radon NUFFT: forward and adjoint Radon
 transforms by gridding, behind the C ABI of include/radon.h."""
-from .radon import Plan, RadonError, fft_test, lib, stage_names, supported_length
+from .radon import Batch, Plan, RadonError, Tuning, autotune, fft_test, lib, stage_names, supported_length
 
-__all__ = ["Plan", "RadonError", "fft_test", "lib", "stage_names", "supported_length"]
+__all__ = ["Batch", "Plan", "RadonError", "Tuning", "autotune", "fft_test", "lib", "stage_names",
+           "supported_length"]

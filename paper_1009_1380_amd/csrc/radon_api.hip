@@ -292,14 +292,14 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
             const int xl = (cx + ntl - 1) % ntl, yu = (cy + ntl - 1) % ntl;
             const int total = run(yu * ntl + xl, 2, 3) + run(yu * ntl + cx, 2, 4) + run(cy * ntl + xl, 1, 3) +
                               run(own, 0, 4);
-            if (total <= kA2Chunk) {
+            const int chunk = p.a2_chunk;
+            if (total <= chunk) {
                 items.push_back({cx, cy, 0, total, -1, 0, 0, 0});
             } else {
-                const int nch = (total + kA2Chunk - 1) / kA2Chunk;
+                const int nch = (total + chunk - 1) / chunk;
                 splits.push_back({cx, cy, slots, nch});
                 for (int k = 0; k < nch; ++k)
-                    items.push_back({cx, cy, k * kA2Chunk, std::min(kA2Chunk, total - k * kA2Chunk), slots + k,
-                                     0, 0, 0});
+                    items.push_back({cx, cy, k * chunk, std::min(chunk, total - k * chunk), slots + k, 0, 0, 0});
                 slots += nch;
             }
         }
@@ -318,8 +318,8 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
                 const int cx1 = (cx + 1) % ntl;
                 n_all += run(cy * ntl + cx1, 0, 4) + run(cy1 * ntl + cx1, 0, 4);
             }
-            for (int s = 0; s < n_all; s += kF3Chunk)
-                fitems.push_back({cx, cy, nbx, s, std::min(kF3Chunk, n_all - s), 0, 0, 0});
+            for (int s = 0; s < n_all; s += p.f3_chunk)
+                fitems.push_back({cx, cy, nbx, s, std::min(p.f3_chunk, n_all - s), 0, 0, 0});
         }
     }
     // longest items first so the tail of each launch is short
@@ -350,7 +350,8 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
     return RADON_OK;
 }
 
-radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int n_det, double sigma, int W) {
+radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int n_det, double sigma, int W,
+                          const radon_tuning& tuning) {
     p.n = n;
     p.n_views = n_views;
     p.n_det = n_det;
@@ -358,12 +359,20 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
     p.sigma = sigma;
     p.G = 2 * n;
     const int G = p.G;
-    // tile size: largest of 32/16/8 dividing G/2 (so tiles do not straddle the
-    // half-plane edge) and at least W (a footprint spans at most two tiles)
+    // tile size: T divides G/2 (tiles do not straddle the half-plane edge) and
+    // T >= W (a footprint spans at most two tiles); default the largest of 32/16/8
     p.T = 0;
-    for (int T : {32, 16, 8})
-        if ((G / 2) % T == 0 && T >= W) { p.T = T; break; }
+    if (tuning.tile) {
+        if ((G / 2) % tuning.tile || tuning.tile < W)
+            return fail(RADON_ERR_UNSUPPORTED, "tile %d does not fit G=%d, W=%d", tuning.tile, G, W);
+        p.T = tuning.tile;
+    } else {
+        for (int T : {32, 16, 8})
+            if ((G / 2) % T == 0 && T >= W) { p.T = T; break; }
+    }
     if (p.T == 0) return fail(RADON_ERR_UNSUPPORTED, "no tile size in {8,16,32} fits G=%d", G);
+    p.a2_chunk = tuning.a2_chunk ? tuning.a2_chunk : kA2Chunk;
+    p.f3_chunk = tuning.f3_chunk ? tuning.f3_chunk : kF3Chunk;
     p.ntl = G / p.T;
     p.n_bins = p.ntl * p.ntl;
     p.n_samples = (int64_t)n_views * n_det + n_views;
@@ -416,6 +425,15 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
 }  // namespace
 
 namespace rn {
+radon_status_t api_fail(radon_status_t st, const char* msg) { return fail(st, "%s", msg); }
+radon_status_t api_ok() { return ok(); }
+radon_status_t api_check_plan(radon_plan_t plan) { return check_plan(plan); }
+radon_status_t api_run_forward(Plan& p, const float* img, float* sino, hipStream_t st) {
+    return run_forward(p, img, sino, st);
+}
+radon_status_t api_run_adjoint(Plan& p, const float* sino, float* img, hipStream_t st) {
+    return run_adjoint(p, sino, img, st);
+}
 bool length_supported(int len) {
     switch (len) {
 #define RN_CASE(L) case L:
@@ -449,6 +467,11 @@ extern "C" {
 
 radon_status_t radon_plan(radon_plan_t* out, int n, const double* angles, int n_views, int n_det,
                           double sigma, int W) {
+    return radon_plan_tuned(out, n, angles, n_views, n_det, sigma, W, nullptr);
+}
+
+radon_status_t radon_plan_tuned(radon_plan_t* out, int n, const double* angles, int n_views, int n_det,
+                                double sigma, int W, const radon_tuning* tuning) {
     if (!out) return fail(RADON_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!angles) return fail(RADON_ERR_INVALID, "angles is NULL");
@@ -468,6 +491,13 @@ radon_status_t radon_plan(radon_plan_t* out, int n, const double* angles, int n_
         return fail(RADON_ERR_UNSUPPORTED, "n_det=%d is not a supported FFT length", n_det);
     if ((int64_t)n_views * n_det + n_views >= (int64_t)1 << 30 || (int64_t)n_views * (n_det / 2 + 1) >= (int64_t)1 << 29)
         return fail(RADON_ERR_UNSUPPORTED, "too many samples");
+    const radon_tuning tn = tuning ? *tuning : radon_tuning{0, 0, 0};
+    if (tn.tile != 0 && tn.tile != 8 && tn.tile != 16 && tn.tile != 32)
+        return fail(RADON_ERR_INVALID, "tile=%d must be 0, 8, 16 or 32", tn.tile);
+    if (tn.a2_chunk != 0 && (tn.a2_chunk < 64 || tn.a2_chunk > kA2Chunk))
+        return fail(RADON_ERR_INVALID, "a2_chunk=%d must be 0 or 64..%d", tn.a2_chunk, kA2Chunk);
+    if (tn.f3_chunk != 0 && (tn.f3_chunk < 256 || tn.f3_chunk > 65536))
+        return fail(RADON_ERR_INVALID, "f3_chunk=%d must be 0 or 256..65536", tn.f3_chunk);
 
     radon_plan_s* plan = new (std::nothrow) radon_plan_s();
     if (!plan) return fail(RADON_ERR_OOM, "host allocation failed");
@@ -476,7 +506,7 @@ radon_status_t radon_plan(radon_plan_t* out, int n, const double* angles, int n_
         delete plan;
         return fail(RADON_ERR_DEVICE, "no HIP device");
     }
-    const radon_status_t s = build_plan(plan->p, n, angles, n_views, n_det, sigma, W);
+    const radon_status_t s = build_plan(plan->p, n, angles, n_views, n_det, sigma, W, tn);
     if (s != RADON_OK) {
         const std::string msg = g_last_error;
         (void)hipDeviceSynchronize();

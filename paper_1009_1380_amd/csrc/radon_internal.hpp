@@ -7,6 +7,7 @@
 
 #include <vector>
 
+#include "../../include/radon.h"
 #include "radon_kernels.hpp"
 
 // Supported FFT lengths (image size n and detector count n_det).
@@ -44,6 +45,7 @@ struct Plan {
     int n_items = 0, n_slots = 0, n_splits = 0;   // spreading work
     int n_fitems = 0;                   // forward interpolation work
     int f3_grid = 0;                    // workgroups of the persistent forward interpolation
+    int a2_chunk = 0, f3_chunk = 0;     // most visits / samples per work item
     float kbS = 0;                      // cubic pieces per unit of t
 
     // device tables
@@ -91,6 +93,15 @@ hipError_t launch_fft_test(int len, int batch, int inverse, const float2* in, fl
                            const float2* tw, hipStream_t st);
 
 bool length_supported(int len);
+
+// Shared with the other translation units of the C ABI (defined in
+// radon_api.hip): error reporting into radon_last_error(), the plan check,
+// and the forward / adjoint kernel sequences enqueued on a stream.
+radon_status_t api_fail(radon_status_t st, const char* msg);
+radon_status_t api_ok();
+radon_status_t api_check_plan(radon_plan_t plan);
+radon_status_t api_run_forward(Plan& p, const float* img, float* sino, hipStream_t st);
+radon_status_t api_run_adjoint(Plan& p, const float* sino, float* img, hipStream_t st);
 
 }  // namespace rn
 

@@ -50,7 +50,26 @@ _SIGS = {
     "radon_fft_test": (_c_int, [_c_int, _c_int, _c_int, _vp, _vp, _vp]),
     "radon_ring_filter": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_solve_bpdn": (_c_int, [_vp, _vp, _vp, ctypes.c_void_p, ctypes.c_void_p, _vp]),
+    "radon_plan_tuned": (_c_int, [ctypes.POINTER(_vp), _c_int, ctypes.POINTER(_c_dbl), _c_int, _c_int, _c_dbl,
+                                  _c_int, ctypes.c_void_p]),
+    "radon_plan_tuning": (_c_int, [_vp, ctypes.c_void_p]),
+    "radon_autotune": (_c_int, [_c_int, ctypes.POINTER(_c_dbl), _c_int, _c_int, _c_dbl, _c_int, _c_int,
+                                ctypes.c_void_p, ctypes.POINTER(_c_dbl), ctypes.POINTER(_c_dbl), _vp]),
+    "radon_batch_create": (_c_int, [ctypes.POINTER(_vp), _c_int, ctypes.POINTER(_vp), _c_int]),
+    "radon_batch_forward": (_c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+    "radon_batch_adjoint": (_c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+    "radon_batch_graphs_recorded": (_c_int, [_vp]),
+    "radon_batch_destroy": (None, [_vp]),
 }
+
+
+class Tuning(ctypes.Structure):
+    """Work decomposition of a plan: bin tile side, most visits per spreading
+    item, most samples per forward-interpolation item (0 = default)."""
+    _fields_ = [("tile", ctypes.c_int), ("a2_chunk", ctypes.c_int), ("f3_chunk", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SolveOpts(ctypes.Structure):
@@ -157,16 +176,27 @@ class Plan:
     INFO_KEYS = ("n", "n_views", "n_det", "W", "G", "T", "n_samples", "n_bins",
                  "n_items", "n_slots", "device_bytes", "n_fitems")
 
-    def __init__(self, n: int, angles, n_det: int, sigma: float = 2.0, W: int = 6):
+    def __init__(self, n: int, angles, n_det: int, sigma: float = 2.0, W: int = 6, tuning=None):
         ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).ravel())
         self.n, self.n_det, self.n_views = int(n), int(n_det), int(ang.size)
         self.sigma, self.W = float(sigma), int(W)
         self.angles = ang.copy()
         h = ctypes.c_void_p()
-        st = lib().radon_plan(ctypes.byref(h), self.n, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                              self.n_views, self.n_det, self.sigma, self.W)
+        angp = ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if tuning is None:
+            st = lib().radon_plan(ctypes.byref(h), self.n, angp, self.n_views, self.n_det, self.sigma, self.W)
+        else:
+            t = Tuning(int(tuning.get("tile", 0)), int(tuning.get("a2_chunk", 0)), int(tuning.get("f3_chunk", 0)))
+            st = lib().radon_plan_tuned(ctypes.byref(h), self.n, angp, self.n_views, self.n_det, self.sigma,
+                                        self.W, ctypes.byref(t))
         _check(st, "radon_plan")
         self._h = h
+
+    def tuning(self) -> dict:
+        """The work decomposition this plan uses (defaults resolved)."""
+        t = Tuning()
+        _check(lib().radon_plan_tuning(self._h, ctypes.byref(t)), "radon_plan_tuning")
+        return t.as_dict()
 
     # -- lifetime
     def close(self):
@@ -317,3 +347,61 @@ def fft_test(x, inverse: bool = False, stream=None):
                                 ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                 _stream_ptr(stream)), "radon_fft_test")
     return out
+
+
+def autotune(n: int, angles, n_det: int, sigma: float = 2.0, W: int = 6, repeats: int = 5, stream=None):
+    """Time candidate work decompositions of a geometry on the device and
+    return (best tuning dict, best ms per forward+adjoint pair, default ms)."""
+    ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).ravel())
+    best, best_ms, def_ms = Tuning(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().radon_autotune(int(n), ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(ang.size),
+                                int(n_det), float(sigma), int(W), int(repeats), ctypes.byref(best),
+                                ctypes.byref(best_ms), ctypes.byref(def_ms), _stream_ptr(stream)),
+           "radon_autotune")
+    return best.as_dict(), best_ms.value, def_ms.value
+
+
+class Batch:
+    """Uneven slices (distinct plans of any sizes) run together: each
+    direction is recorded once per set of buffers into one HIP graph whose
+    branches run slices side by side, then replayed with a single launch."""
+
+    def __init__(self, plans, n_branches: int = 4):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().radon_batch_create(ctypes.byref(h), len(self.plans), arr, int(n_branches)),
+               "radon_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().radon_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def graphs_recorded(self) -> int:
+        return int(lib().radon_batch_graphs_recorded(self._h))
+
+    def _ptrs(self, tensors, shapes, name):
+        if len(tensors) != len(self.plans):
+            raise ValueError(f"{name}: {len(tensors)} tensors for {len(self.plans)} slices")
+        return (ctypes.c_void_p * len(tensors))(*[_dev_ptr(t, s, f"{name}[{i}]").value
+                                                 for i, (t, s) in enumerate(zip(tensors, shapes))])
+
+    def forward(self, imgs, outs, stream=None):
+        ins = self._ptrs(imgs, [(p.n, p.n) for p in self.plans], "imgs")
+        ous = self._ptrs(outs, [(p.n_views, p.n_det) for p in self.plans], "outs")
+        _check(lib().radon_batch_forward(self._h, ins, ous, _stream_ptr(stream)), "radon_batch_forward")
+        return outs
+
+    def adjoint(self, sinos, outs, stream=None):
+        ins = self._ptrs(sinos, [(p.n_views, p.n_det) for p in self.plans], "sinos")
+        ous = self._ptrs(outs, [(p.n, p.n) for p in self.plans], "outs")
+        _check(lib().radon_batch_adjoint(self._h, ins, ous, _stream_ptr(stream)), "radon_batch_adjoint")
+        return outs
