@@ -160,6 +160,81 @@ def solve_times(dev, repeats: int = 3):
     return out
 
 
+BATCH_SIZES = (512, 1024, 1536, 2048, 2560)
+BATCH_VIEWS = (90, 180, 360, 720, 1024)
+
+
+def batch_times(dev, n_slices: int = 64, repeats: int = 5, seed: int = 0):
+    """Uneven slices: n_slices slices, side uniform in BATCH_SIZES, view count
+    uniform in BATCH_VIEWS (angles uniform in [0, pi)), detector bins = side.
+    One step = forward + adjoint of every slice. Three ways: per-slice calls
+    back to back on one stream; the batch's two HIP graphs (forward, adjoint)
+    with the default decomposition; the same with every distinct shape's
+    decomposition chosen by the autotuner."""
+    import numpy as np
+    import torch
+
+    from paper_1009_1380_amd import Batch, Plan, autotune
+    from radon_inputs import random_image, uniform_angles
+
+    rng = np.random.default_rng(seed)
+    shapes = [(int(rng.choice(BATCH_SIZES)), int(rng.choice(BATCH_VIEWS))) for _ in range(n_slices)]
+    imgs = [torch.from_numpy(random_image(seed + k, n)).to(dev) for k, (n, _) in enumerate(shapes)]
+    sinos = [torch.empty((v, n), device=dev) for n, v in shapes]
+    backs = [torch.empty((n, n), device=dev) for n, _ in shapes]
+    samples = sum(n * v for n, v in shapes)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(repeats):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / repeats
+
+    def run_modes(plans):
+        def per_slice():
+            for p, x, y, z in zip(plans, imgs, sinos, backs):
+                p.forward(x, out=y, stream=stream)
+                p.adjoint(y, out=z, stream=stream)
+        batch = Batch(plans, n_branches=4)
+
+        def graphs():
+            batch.forward(imgs, sinos, stream=stream)
+            batch.adjoint(sinos, backs, stream=stream)
+        return timed(per_slice), timed(graphs)
+
+    plans = [Plan(n, uniform_angles(v), n) for n, v in shapes]
+    ms_slice, ms_graph = run_modes(plans)
+    del plans
+    t0 = time.perf_counter()
+    tuned = {}
+    for n, v in sorted(set(shapes)):
+        tuned[(n, v)] = autotune(n, uniform_angles(v), n, repeats=3, stream=stream)
+    t_tune = time.perf_counter() - t0
+    plans = [Plan(n, uniform_angles(v), n, tuning=tuned[(n, v)][0]) for n, v in shapes]
+    ms_slice_t, ms_graph_t = run_modes(plans)
+    del plans
+    changed = sum(1 for k, (best, _, _) in tuned.items() if best != {"tile": 32, "a2_chunk": 512, "f3_chunk": 2048})
+
+    def gs(ms):
+        return round(samples / (ms * 1e-3) / 1e9, 3)
+    return {
+        "workload": f"{n_slices} uneven slices: side uniform in {list(BATCH_SIZES)}, views uniform in "
+                    f"{list(BATCH_VIEWS)}, detector bins = side; one step = forward + adjoint of every slice",
+        "samples_per_step": samples,
+        "per_slice_calls": {"ms_per_step": round(ms_slice, 3), "Gsamples_per_s": gs(ms_slice)},
+        "graph_batch": {"ms_per_step": round(ms_graph, 3), "Gsamples_per_s": gs(ms_graph)},
+        "per_slice_calls_autotuned": {"ms_per_step": round(ms_slice_t, 3), "Gsamples_per_s": gs(ms_slice_t)},
+        "graph_batch_autotuned": {"ms_per_step": round(ms_graph_t, 3), "Gsamples_per_s": gs(ms_graph_t)},
+        "autotune": {"seconds": round(t_tune, 2), "shapes": len(tuned), "shapes_off_default": changed},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +243,7 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=1024, help="views in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the reduced-view solve timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-slice batch timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -308,6 +384,9 @@ def main():
     if not args.no_solve:
         print("bench: timing the reduced-view solves", file=sys.stderr, flush=True)
         line["solve"] = solve_times(dev)
+    if not args.no_batch:
+        print("bench: timing the uneven-slice batch", file=sys.stderr, flush=True)
+        line["batch"] = batch_times(dev)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_views)
