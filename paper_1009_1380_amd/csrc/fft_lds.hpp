@@ -219,6 +219,100 @@ __device__ __forceinline__ void fft_lds(float2* buf, const float2* __restrict__ 
     fft_passes<LEN, 0, 1, B, NT, lds_ls(LEN)>(buf, tw, tid);
 }
 
+// ---- register-in / register-out forms
+// The first radix pass can take its inputs straight from registers and the
+// last pass can leave its outputs in registers, which saves the LDS round
+// trips of staging the input and of reading back the result (and two
+// barriers). For B lines of length LEN with plan r[0..np-1] (np >= 2):
+//   first pass: butterfly b = tid + it*NT (< B*NB0, NB0 = LEN/R0) of line
+//     b / NB0 holds x[bf + m*NB0], m < R0 (bf = b mod NB0), in v[it][m];
+//   last pass: butterfly b (< B*NBL, NBL = LEN/RL) leaves X[bf + m*NBL] in
+//     out[it][m].
+template <int LEN, int B, int NT>
+struct FftRegIO {
+    static constexpr RadixPlan plan = make_plan(LEN);
+    static constexpr int NP = plan.np;
+    static constexpr int R0 = plan.r[0];
+    static constexpr int NB0 = LEN / R0;
+    static constexpr int IT0 = (NB0 * B + NT - 1) / NT;
+    static constexpr int RL = plan.r[NP - 1];
+    static constexpr int NBL = LEN / RL;
+    static constexpr int ITL = (NBL * B + NT - 1) / NT;
+    static constexpr int LS = lds_ls(LEN);
+};
+
+// First pass (L = 1, no twiddles) from registers into LDS; v is clobbered.
+// The caller barriers afterwards.
+template <int LEN, int B, int NT, int IT, int R>
+__device__ __forceinline__ void fft_first_from_regs(float2 (&v)[IT][R], float2* buf, int tid) {
+    using IO = FftRegIO<LEN, B, NT>;
+    static_assert(IT == IO::IT0 && R == IO::R0, "register layout of the first pass");
+    constexpr bool FULL = ((IO::NB0 * B) % NT) == 0;
+#pragma unroll
+    for (int it = 0; it < IO::IT0; ++it) {
+        const int b = tid + it * NT;
+        if (FULL || b < IO::NB0 * B) {
+            const int line = b / IO::NB0;
+            const int bf = b - line * IO::NB0;
+            Dft<IO::R0>::run(v[it]);
+            float2* dst = buf + line * IO::LS;
+#pragma unroll
+            for (int m = 0; m < IO::R0; ++m) dst[lds_pad(bf * IO::R0 + m)] = v[it][m];
+        }
+    }
+}
+
+// Passes P .. np-2 in LDS (each ends with a barrier).
+template <int LEN, int P, int L, int B, int NT, int LS>
+__device__ __forceinline__ void fft_mid_passes(float2* buf, const float2* __restrict__ tw, int tid) {
+    constexpr RadixPlan plan = make_plan(LEN);
+    if constexpr (P < plan.np - 1) {
+        constexpr int R = plan.r[P];
+        stockham_pass<LEN, R, L, B, NT, LS>(buf, tw, tid);
+        fft_mid_passes<LEN, P + 1, L * R, B, NT, LS>(buf, tw, tid);
+    }
+}
+
+// Last pass from LDS into registers (no LDS writes, no trailing barrier).
+template <int LEN, int B, int NT, int IT, int RR>
+__device__ __forceinline__ void fft_last_to_regs(const float2* buf, const float2* __restrict__ tw, int tid,
+                                                 float2 (&out)[IT][RR]) {
+    using IO = FftRegIO<LEN, B, NT>;
+    static_assert(IT == IO::ITL && RR == IO::RL, "register layout of the last pass");
+    constexpr int R = IO::RL;
+    constexpr bool FULL = ((IO::NBL * B) % NT) == 0;
+#pragma unroll
+    for (int it = 0; it < IO::ITL; ++it) {
+        const int b = tid + it * NT;
+        if (FULL || b < IO::NBL * B) {
+            const int line = b / IO::NBL;
+            const int bf = b - line * IO::NBL;
+            const float2* src = buf + line * IO::LS;
+#pragma unroll
+            for (int m = 0; m < R; ++m) out[it][m] = src[lds_pad(bf + m * IO::NBL)];
+            float2 w[R];
+            twiddle_powers<R>(tw[bf], w);
+#pragma unroll
+            for (int m = 1; m < R; ++m) out[it][m] = cmul(out[it][m], w[m]);
+            Dft<R>::run(out[it]);
+        }
+    }
+}
+
+// Whole transform with register input and output: first pass from v, middle
+// passes in LDS, last pass into out. The caller barriers before the call if
+// the LDS lines are still being read.
+template <int LEN, int B, int NT, int I0, int R0, int IL, int RL>
+__device__ __forceinline__ void fft_regs(float2 (&v)[I0][R0], float2* buf, const float2* __restrict__ tw, int tid,
+                                         float2 (&out)[IL][RL]) {
+    using IO = FftRegIO<LEN, B, NT>;
+    static_assert(IO::NP >= 2, "register form needs at least two passes");
+    fft_first_from_regs<LEN, B, NT>(v, buf, tid);
+    __syncthreads();
+    fft_mid_passes<LEN, 1, IO::R0, B, NT, IO::LS>(buf, tw, tid);
+    fft_last_to_regs<LEN, B, NT>(buf, tw, tid, out);
+}
+
 // Threads per workgroup used for a transform of B lines of length LEN.
 // Threads for the row/column kernels, whose per-thread register arrays shrink
 // with more threads: 512 from length 1024 on.

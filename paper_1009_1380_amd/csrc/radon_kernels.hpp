@@ -181,47 +181,91 @@ __global__ __launch_bounds__(NT) void k_f1_rows(const float* __restrict__ img, f
 // ---------------------------------------------------------------- F2
 // One half-plane line mx per workgroup: FFT along py of T1[mx][.] into
 // grid[mx][my], my = 2k + r from two length-n transforms done one after the
-// other in one LDS line (the input and the r = 0 result wait in registers).
+// other in one LDS line. The input and the r = 0 result wait in registers;
+// each transform takes its first pass from registers and leaves its last
+// pass in registers (FftRegIO), so the line is read from HBM straight into
+// the first butterflies and the results go from the last butterflies
+// straight to HBM.
 template <int NL, int NT>
 __global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, float2* __restrict__ grid,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
-    constexpr int PE = (NL + NT - 1) / NT;
     __shared__ float2 lds[lds_ls(NL)];
     const int tid = threadIdx.x;
     const int mx = blockIdx.x;
     const float2* src = T1 + (size_t)mx * NL;
-    float2 c[PE], z0[PE];
-#pragma unroll
-    for (int e = 0; e < PE; ++e) {
-        const int i = tid + e * NT;
-        if (i < NL) {
-            c[e] = src[i];
-            lds[lds_pad((i + NL / 2) % NL)] = c[e];
-        }
-    }
-    __syncthreads();
-    fft_lds<NL, 1, NT>(lds, tw, tid);
-#pragma unroll
-    for (int e = 0; e < PE; ++e) {
-        const int k = tid + e * NT;
-        if (k < NL) z0[e] = lds[lds_pad(k)];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < PE; ++e) {
-        const int i = tid + e * NT;
-        if (i < NL) lds[lds_pad((i + NL / 2) % NL)] = cmul(c[e], shift[i]);
-    }
-    __syncthreads();
-    fft_lds<NL, 1, NT>(lds, tw, tid);
     float4* dst = reinterpret_cast<float4*>(grid + (size_t)mx * (2 * NL));
+    using IO = FftRegIO<NL, 1, NT>;
+    if constexpr (IO::NP >= 2) {
+        // FFT position p holds py = p (mod n), i.e. T1 index i = (p + n/2) mod n
+        float2 c[IO::IT0][IO::R0], v[IO::IT0][IO::R0];
+        float2 X0[IO::ITL][IO::RL], X1[IO::ITL][IO::RL];
 #pragma unroll
-    for (int e = 0; e < PE; ++e) {
-        const int k = tid + e * NT;
-        if (k < NL) {
-            const float2 o = lds[lds_pad(k)];
-            dst[k] = make_float4(z0[e].x, z0[e].y, o.x, o.y);
+        for (int it = 0; it < IO::IT0; ++it) {
+            const int b = tid + it * NT;
+#pragma unroll
+            for (int m = 0; m < IO::R0; ++m) {
+                const int i = (b + m * IO::NB0 + NL / 2) % NL;
+                c[it][m] = (b < IO::NB0) ? src[i] : make_float2(0.f, 0.f);
+                v[it][m] = c[it][m];
+            }
+        }
+        fft_regs<NL, 1, NT>(v, lds, tw, tid, X0);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IO::IT0; ++it) {
+            const int b = tid + it * NT;
+#pragma unroll
+            for (int m = 0; m < IO::R0; ++m) {
+                const int i = (b + m * IO::NB0 + NL / 2) % NL;
+                v[it][m] = (b < IO::NB0) ? cmul(c[it][m], shift[i]) : make_float2(0.f, 0.f);
+            }
+        }
+        fft_regs<NL, 1, NT>(v, lds, tw, tid, X1);
+#pragma unroll
+        for (int it = 0; it < IO::ITL; ++it) {
+            const int b = tid + it * NT;
+            if (b < IO::NBL) {
+#pragma unroll
+                for (int m = 0; m < IO::RL; ++m) {
+                    const int k = b + m * IO::NBL;
+                    dst[k] = make_float4(X0[it][m].x, X0[it][m].y, X1[it][m].x, X1[it][m].y);
+                }
+            }
+        }
+    } else {
+        constexpr int PE = (NL + NT - 1) / NT;
+        float2 c[PE], z0[PE];
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int i = tid + e * NT;
+            if (i < NL) {
+                c[e] = src[i];
+                lds[lds_pad((i + NL / 2) % NL)] = c[e];
+            }
+        }
+        __syncthreads();
+        fft_lds<NL, 1, NT>(lds, tw, tid);
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int k = tid + e * NT;
+            if (k < NL) z0[e] = lds[lds_pad(k)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int i = tid + e * NT;
+            if (i < NL) lds[lds_pad((i + NL / 2) % NL)] = cmul(c[e], shift[i]);
+        }
+        __syncthreads();
+        fft_lds<NL, 1, NT>(lds, tw, tid);
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int k = tid + e * NT;
+            if (k < NL) {
+                const float2 o = lds[lds_pad(k)];
+                dst[k] = make_float4(z0[e].x, z0[e].y, o.x, o.y);
+            }
         }
     }
 }
@@ -646,48 +690,80 @@ __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__
 // ---------------------------------------------------------------- A3
 // One grid line mx per workgroup: h[p] = sum_my H[my] e^{+2 pi i my p/G} for
 // the n rows p = -n/2..n/2-1 = IFFT_n(H_even)[p] + e^{i pi p/n} IFFT_n(H_odd)[p];
-// the two inverse transforms share one LDS line, one after the other.
+// the two inverse transforms share one LDS line, one after the other, each
+// with register input and output (FftRegIO); the inverse is conj(FFT(conj)).
 template <int NL, int NT>
 __global__ __launch_bounds__(NT) void k_a3_cols(const float2* __restrict__ grid, float2* __restrict__ T1,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
-    constexpr int PE = (NL + NT - 1) / NT;
     __shared__ float2 lds[lds_ls(NL)];
     const int tid = threadIdx.x;
     const int mx = blockIdx.x;
     const float4* src = reinterpret_cast<const float4*>(grid + (size_t)mx * (2 * NL));
-    float2 odd[PE], ev[PE];
-#pragma unroll
-    for (int e = 0; e < PE; ++e) {
-        const int k = tid + e * NT;
-        if (k < NL) {
-            const float4 v = src[k];
-            lds[lds_pad(k)] = make_float2(v.x, -v.y);        // conj for the inverse
-            odd[e] = make_float2(v.z, -v.w);
-        }
-    }
-    __syncthreads();
-    fft_lds<NL, 1, NT>(lds, tw, tid);
-#pragma unroll
-    for (int e = 0; e < PE; ++e) {
-        const int i = tid + e * NT;
-        if (i < NL) ev[e] = cconj(lds[lds_pad((i + NL / 2) % NL)]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < PE; ++e) {
-        const int k = tid + e * NT;
-        if (k < NL) lds[lds_pad(k)] = odd[e];
-    }
-    __syncthreads();
-    fft_lds<NL, 1, NT>(lds, tw, tid);
     float2* dst = T1 + (size_t)mx * NL;
+    using IO = FftRegIO<NL, 1, NT>;
+    if constexpr (IO::NP >= 2) {
+        float2 ve[IO::IT0][IO::R0], vo[IO::IT0][IO::R0];
+        float2 E[IO::ITL][IO::RL], O[IO::ITL][IO::RL];
 #pragma unroll
-    for (int e = 0; e < PE; ++e) {
-        const int i = tid + e * NT;
-        if (i < NL) {
-            const float2 o = cconj(lds[lds_pad((i + NL / 2) % NL)]);
-            dst[i] = cadd(ev[e], cmul(cconj(shift[i]), o));
+        for (int it = 0; it < IO::IT0; ++it) {
+            const int b = tid + it * NT;
+#pragma unroll
+            for (int m = 0; m < IO::R0; ++m) {
+                const float4 g = (b < IO::NB0) ? src[b + m * IO::NB0] : make_float4(0.f, 0.f, 0.f, 0.f);
+                ve[it][m] = make_float2(g.x, -g.y);          // conj for the inverse
+                vo[it][m] = make_float2(g.z, -g.w);
+            }
+        }
+        fft_regs<NL, 1, NT>(ve, lds, tw, tid, E);
+        __syncthreads();
+        fft_regs<NL, 1, NT>(vo, lds, tw, tid, O);
+        // FFT position q is row p = q (mod n), stored at i = (q + n/2) mod n
+#pragma unroll
+        for (int it = 0; it < IO::ITL; ++it) {
+            const int b = tid + it * NT;
+            if (b < IO::NBL) {
+#pragma unroll
+                for (int m = 0; m < IO::RL; ++m) {
+                    const int i = (b + m * IO::NBL + NL / 2) % NL;
+                    dst[i] = cadd(cconj(E[it][m]), cmul(cconj(shift[i]), cconj(O[it][m])));
+                }
+            }
+        }
+    } else {
+        constexpr int PE = (NL + NT - 1) / NT;
+        float2 odd[PE], ev[PE];
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int k = tid + e * NT;
+            if (k < NL) {
+                const float4 v = src[k];
+                lds[lds_pad(k)] = make_float2(v.x, -v.y);        // conj for the inverse
+                odd[e] = make_float2(v.z, -v.w);
+            }
+        }
+        __syncthreads();
+        fft_lds<NL, 1, NT>(lds, tw, tid);
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int i = tid + e * NT;
+            if (i < NL) ev[e] = cconj(lds[lds_pad((i + NL / 2) % NL)]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int k = tid + e * NT;
+            if (k < NL) lds[lds_pad(k)] = odd[e];
+        }
+        __syncthreads();
+        fft_lds<NL, 1, NT>(lds, tw, tid);
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int i = tid + e * NT;
+            if (i < NL) {
+                const float2 o = cconj(lds[lds_pad((i + NL / 2) % NL)]);
+                dst[i] = cadd(ev[e], cmul(cconj(shift[i]), o));
+            }
         }
     }
 }
