@@ -54,9 +54,9 @@ hipError_t launch_a2(const Plan& p, hipStream_t st) {
 hipError_t launch_a2_reduce(const Plan& p, hipStream_t st) {
     if (p.n_splits == 0) return hipSuccess;
     switch (p.T) {
-        case 8: hipLaunchKernelGGL((k_a2_reduce<8>), dim3(p.n_splits), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
-        case 16: hipLaunchKernelGGL((k_a2_reduce<16>), dim3(p.n_splits), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
-        case 32: hipLaunchKernelGGL((k_a2_reduce<32>), dim3(p.n_splits), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
+        case 8: hipLaunchKernelGGL((k_a2_reduce<8>), dim3(p.n_splits, (8 * 8 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
+        case 16: hipLaunchKernelGGL((k_a2_reduce<16>), dim3(p.n_splits, (16 * 16 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
+        case 32: hipLaunchKernelGGL((k_a2_reduce<32>), dim3(p.n_splits, (32 * 32 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

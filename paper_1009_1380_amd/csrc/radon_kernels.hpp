@@ -54,6 +54,18 @@ __device__ __forceinline__ float kb_weight(float t, const float4* __restrict__ t
     return t < half_w ? w : 0.0f;
 }
 
+// Footprint point k (0..W-1) of a sample with fraction f lies at distance
+// |f + W/2 - 1 - k|; only the two outer points (k = 0, W-1) can reach the
+// support edge W/2, where phi jumps from 1/I0(beta) (9e-4 for W = 4) to 0.
+// Whether they are inside is decided once per sample in float64 (the record's
+// edge flags, see SampleRec); the float32 distance is clamped to the largest
+// float below W/2 so that an inside point never rounds onto the edge.
+__device__ __forceinline__ float kb_edge(float half_w) { return __int_as_float(__float_as_int(half_w) - 1); }
+template <int W>
+__device__ __forceinline__ float kb_dist(float f, int k, float edge) {
+    return fminf(fabsf(f + (float)(W / 2 - 1 - k)), edge);
+}
+
 // The same weight with an early exit outside the support (fewer registers
 // when the caller keeps many weights live).
 __device__ __forceinline__ float kb_weight_br(float t, const float4* __restrict__ tab, float S, float half_w) {
@@ -69,6 +81,7 @@ __device__ __forceinline__ float kb_weight_br(float t, const float4* __restrict_
 #endif
 
 struct SampleGeom {
+    double u, v;     // grid coordinates
     int bu, bv;      // floor(u), floor(v)
     float fu, fv;    // u - floor(u), v - floor(v), rounded to float32
 };
@@ -84,6 +97,8 @@ __device__ __forceinline__ SampleGeom sample_geom(double c, double s, int q, int
     double v = fq * s;
     double fbu = floor(u), fbv = floor(v);
     SampleGeom g;
+    g.u = u;
+    g.v = v;
     g.bu = (int)fbu;
     g.bv = (int)fbv;
     g.fu = (float)(u - fbu);
@@ -309,7 +324,9 @@ struct TileItem {
 
 // Per-sample record in sorted order, built once per plan so that the
 // gridding kernels need no geometry of their own:
-//   org   footprint origin, o_u | o_v << 16 (centred grid coordinates)
+//   org   footprint origin o_u (bits 0..12) and o_v (bits 16..28), centred
+//         grid coordinates; bits 13/14 (u) and 29/30 (v): the first / last
+//         footprint point lies outside the support, |u - m| >= W/2 in float64
 //   fu,fv u - floor(u), v - floor(v) (float32, as sample_geom gives them)
 //   info  bits 0..28: index a*(N/2+1) + t of the sample's ray-spectrum entry
 //         (t = |q|, or N/2 for both Nyquist samples); bit 29: q in (-N/2, 0)
@@ -321,6 +338,9 @@ struct SampleRec {
     float fu, fv;
     int info;
 };
+constexpr int REC_ORG_MASK = (1 << 13) - 1;
+constexpr int REC_U_NEAR_OUT = 1 << 13, REC_U_FAR_OUT = 1 << 14;
+constexpr int REC_V_NEAR_OUT = 1 << 29, REC_V_FAR_OUT = 1 << 30;
 constexpr int REC_IDX_MASK = (1 << 29) - 1;
 constexpr int REC_CONJ = 1 << 29;
 constexpr int REC_MIRROR = 1 << 30;
@@ -373,6 +393,7 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
     const int tid = threadIdx.x;
     const int ntl = G / T;
     const float hw = 0.5f * (float)W;
+    const float edge = kb_edge(hw);
 
     for (int e = tid; e < NKB; e += NT) kbt[e] = kbc[e];
 
@@ -410,16 +431,19 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
             else pos = s3 + (u - n2);
             const SampleRec r = load_rec(recs, pos);
             if (!((unsigned)r.info & REC_F3)) continue;
-            const int ox = wrap_g((r.org & 0xffff) - x0, G);   // in [0, 2T)
-            const int oy = wrap_g((r.org >> 16) - y0, G);
+            const int ox = wrap_g((r.org & REC_ORG_MASK) - x0, G);   // in [0, 2T)
+            const int oy = wrap_g(((r.org >> 16) & REC_ORG_MASK) - y0, G);
             float wy[W];
 #pragma unroll
-            for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(fabsf(r.fv + (float)(W / 2 - 1 - gm)), kbt, kbS, hw);
+            for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(kb_dist<W>(r.fv, gm, edge), kbt, kbS, hw);
+            if (r.org & REC_V_NEAR_OUT) wy[0] = 0.f;
+            if (r.org & REC_V_FAR_OUT) wy[W - 1] = 0.f;
             const float2* src = tile + ox * P + oy;
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
             for (int al = 0; al < W; ++al) {
-                const float wx = kb_weight(fabsf(r.fu + (float)(W / 2 - 1 - al)), kbt, kbS, hw);
+                float wx = kb_weight(kb_dist<W>(r.fu, al, edge), kbt, kbS, hw);
+                if ((al == 0 && (r.org & REC_U_NEAR_OUT)) || (al == W - 1 && (r.org & REC_U_FAR_OUT))) wx = 0.f;
                 float2 racc = make_float2(0.f, 0.f);
 #pragma unroll
                 for (int gm = 0; gm < W; ++gm) {
@@ -555,6 +579,7 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
     const TileItem it = items[blockIdx.x];
     const int ntl = G / T;
     const float hw = 0.5f * (float)W;
+    const float edge = kb_edge(hw);
 
     for (int e = tid; e < P * P; e += A2_NT) acc[e] = 0ull;
     for (int e = tid; e < NKB; e += A2_NT) kbt[e] = kbc[e];
@@ -585,19 +610,21 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
             const SampleRec r = load_rec(recs, pos);
             float2 Y = Yh[r.info & REC_IDX_MASK];
             if (r.info & REC_CONJ) Y = cconj(Y);
-            int ox = (r.org & 0xffff) - x0;
-            int oy = (r.org >> 16) - y0;
+            int ox = (r.org & REC_ORG_MASK) - x0;
+            int oy = ((r.org >> 16) & REC_ORG_MASK) - y0;
             if (ox >= G / 2) ox -= G;
             if (ox < -G / 2) ox += G;
             if (oy >= G / 2) oy -= G;
             if (oy < -G / 2) oy += G;
             base[k] = (ox + W - 1) * P + (oy + W - 1);
 #pragma unroll
-            for (int al = 0; al < W; ++al)
-                wx[k][al] = RN_A2_KB(fabsf(r.fu + (float)(W / 2 - 1 - al)), kbt, kbS, hw);
+            for (int al = 0; al < W; ++al) wx[k][al] = RN_A2_KB(kb_dist<W>(r.fu, al, edge), kbt, kbS, hw);
+            if (r.org & REC_U_NEAR_OUT) wx[k][0] = 0.f;
+            if (r.org & REC_U_FAR_OUT) wx[k][W - 1] = 0.f;
 #pragma unroll
             for (int gm = 0; gm < W; ++gm) {
-                const float wy = RN_A2_KB(fabsf(r.fv + (float)(W / 2 - 1 - gm)), kbt, kbS, hw);
+                float wy = RN_A2_KB(kb_dist<W>(r.fv, gm, edge), kbt, kbS, hw);
+                if ((gm == 0 && (r.org & REC_V_NEAR_OUT)) || (gm == W - 1 && (r.org & REC_V_FAR_OUT))) wy = 0.f;
                 ywy[k][gm] = make_float2(Y.x * wy, Y.y * wy);
                 mx_abs = fmaxf(mx_abs, fmaxf(fabsf(ywy[k][gm].x), fabsf(ywy[k][gm].y)));
             }
@@ -666,7 +693,8 @@ __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__
     const int x0 = sp.cx * T, y0 = sp.cy * T;
     const int my0 = mod_pos(y0 - G / 2, G);
     const float2* src = partials + (size_t)sp.first_slot * T * T;
-    for (int e = threadIdx.x; e < xvalid * T; e += 256) {
+    // blockIdx.y picks 256 of the tile's points, one per thread
+    for (int e = blockIdx.y * 256 + threadIdx.x; e < xvalid * T && e < (blockIdx.y + 1) * 256; e += 256) {
         // slots are added in order; the loads of eight slots are issued together
         float2 s = make_float2(0.f, 0.f);
         int k = 0;

@@ -75,8 +75,16 @@ __global__ __launch_bounds__(256) void k_sample_recs(const int* __restrict__ per
         idx = mirror ? a * HQ + ND / 2 : a * HQ - q;
         flags = mirror ? REC_MIRROR : REC_CONJ;
     }
+    // the outer footprint points m = floor - W/2 + 1 and floor + W/2 are inside
+    // the support iff |coordinate - m| < W/2, decided in float64
+    const double hw = 0.5 * W;
+    int edges = 0;
+    if (!(fabs(g.u - (double)(g.bu - W / 2 + 1)) < hw)) edges |= REC_U_NEAR_OUT;
+    if (!(fabs(g.u - (double)(g.bu + W / 2)) < hw)) edges |= REC_U_FAR_OUT;
+    if (!(fabs(g.v - (double)(g.bv - W / 2 + 1)) < hw)) edges |= REC_V_NEAR_OUT;
+    if (!(fabs(g.v - (double)(g.bv + W / 2)) < hw)) edges |= REC_V_FAR_OUT;
     int4 r;
-    r.x = footprint_origin(g.bu, W, G) | (footprint_origin(g.bv, W, G) << 16);
+    r.x = footprint_origin(g.bu, W, G) | (footprint_origin(g.bv, W, G) << 16) | edges;
     r.y = __float_as_int(g.fu);
     r.z = __float_as_int(g.fv);
     r.w = (int)((unsigned)idx | (unsigned)flags | (eval ? REC_F3 : 0u));

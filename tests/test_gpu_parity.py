@@ -365,3 +365,34 @@ def test_fbp_reconstructs_gaussian():
     xs = np.arange(n) - n / 2
     inside = np.sqrt(xs[None, :] ** 2 + xs[:, None] ** 2) < n / 2 - 2
     assert rel(r[inside], x[inside]) < 3e-4
+
+
+# ------------------------------------------------------------------ kernel widths and the largest size
+
+@pytest.mark.parametrize("W", [4, 8])
+@pytest.mark.parametrize("n,n_det,nv", [(16, 16, 9), (64, 80, 31), (128, 128, 45)])
+def test_other_kernel_widths_vs_oracle(W, n, n_det, nv):
+    """W = 4 and W = 8 (the plan's other widths) against the oracle with the same W."""
+    note(f"W={W} n={n} n_det={n_det} nv={nv}")
+    ang = special_angles(nv, 3 * n + W)
+    x = random_image(n + W, n)
+    y = random_sinogram(n + W + 1, nv, n_det)
+    plan = Plan(n, ang, n_det, W=W)
+    yg = plan.forward(to_dev(x)).cpu().numpy()
+    ag = plan.adjoint(to_dev(y)).cpu().numpy()
+    assert rel(yg, grid_forward(x.astype(np.float64), ang, n_det, W=W)) < TOL_GRID
+    assert rel(ag, grid_adjoint(y.astype(np.float64), ang, n, W=W)) < TOL_GRID
+
+
+def test_largest_supported_size_vs_oracle():
+    """n = n_det = 4096 (the largest FFT length; G = 8192) on a few views."""
+    note("n=4096 nv=6")
+    n, nv = 4096, 6
+    ang = special_angles(nv, 11)
+    x = random_image(4096, n)
+    y = random_sinogram(4097, nv, n)
+    plan = Plan(n, ang, n)
+    yg = plan.forward(to_dev(x)).cpu().numpy()
+    ag = plan.adjoint(to_dev(y)).cpu().numpy()
+    assert rel(yg, grid_forward(x.astype(np.float64), ang, n)) < TOL_GRID
+    assert rel(ag, grid_adjoint(y.astype(np.float64), ang, n)) < TOL_GRID
