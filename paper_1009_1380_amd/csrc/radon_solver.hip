@@ -75,16 +75,27 @@ __global__ __launch_bounds__(SV_NT) void k_sv_final(const double* __restrict__ p
 }
 
 // m[d] = mean over views of (b - z)[., d] (z may be null: m = mean of b).
+// A block takes 32 detectors; its 8 thread groups sum every 8th view, and the
+// 8 group sums are added in group order.
 __global__ __launch_bounds__(256) void k_sv_colmean(const float* __restrict__ b, const float* __restrict__ z,
                                                    int nv, int N, double* __restrict__ m) {
-    const int d = blockIdx.x * 256 + threadIdx.x;
-    if (d >= N) return;
+    __shared__ double part[8][32];
+    const int dl = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int d = blockIdx.x * 32 + dl;
     double s = 0.0;
-    for (int a = 0; a < nv; ++a) {
-        const size_t i = (size_t)a * N + d;
-        s += (double)b[i] - (z ? (double)z[i] : 0.0);
+    if (d < N) {
+        for (int a = g; a < nv; a += 8) {
+            const size_t i = (size_t)a * N + d;
+            s += (double)b[i] - (z ? (double)z[i] : 0.0);
+        }
     }
-    m[d] = s / nv;
+    part[g][dl] = s;
+    __syncthreads();
+    if (g == 0 && d < N) {
+        double t = part[0][dl];
+        for (int k = 1; k < 8; ++k) t += part[k][dl];
+        m[d] = t / nv;
+    }
 }
 
 // ring[d] = m[d] - (Q Q^T m)[d]  (one block).
@@ -127,56 +138,6 @@ __global__ __launch_bounds__(SV_NT) void k_sv_resid(const float* __restrict__ b,
     if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = t;
 }
 
-// partials for the l1 projection of v = x + c h at threshold lam (device):
-// slot 0: sum max(|v| - lam, 0), slot 1: count(|v| > lam).
-__global__ __launch_bounds__(SV_NT) void k_sv_l1_partial(const float* __restrict__ x, const float* __restrict__ h,
-                                                        double c, const double* __restrict__ lam, size_t n,
-                                                        double* __restrict__ part) {
-    __shared__ double sh[SV_NT / 64];
-    const double L = *lam;
-    double s = 0.0, k = 0.0;
-    for (size_t i = (size_t)blockIdx.x * SV_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * SV_NT) {
-        const float v = (float)((double)x[i] + c * (double)h[i]);
-        const double a = fabs((double)v);
-        if (a > L) { s += a - L; k += 1.0; }
-    }
-    double t = block_reduce<false>(s, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-    t = block_reduce<false>(k, sh);
-    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = t;
-}
-
-// One Newton step on the threshold: with S = sum max(|v| - lam, 0) and K the
-// count above lam (from fin[0], fin[1]), lam += (S - tau)/K while S > tau.
-__global__ void k_sv_l1_newton(const double* __restrict__ fin, double tau, double* __restrict__ lam) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const double S = fin[0], K = fin[1];
-        if (S > tau && K > 0) *lam = *lam + (S - tau) / K;
-    }
-}
-
-// xn = soft(x + c h, lam); partials: slot 0 sum (-h) (xn - x) (= g . dx),
-// slot 1 sum |xn|.
-__global__ __launch_bounds__(SV_NT) void k_sv_soft(const float* __restrict__ x, const float* __restrict__ h,
-                                                  double c, const double* __restrict__ lam, size_t n,
-                                                  float* __restrict__ xn, double* __restrict__ part) {
-    __shared__ double sh[SV_NT / 64];
-    const double L = *lam;
-    double s0 = 0.0, s1 = 0.0;
-    for (size_t i = (size_t)blockIdx.x * SV_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * SV_NT) {
-        const float v = (float)((double)x[i] + c * (double)h[i]);
-        const double a = fabs((double)v) - L;
-        const float o = a > 0 ? (float)copysign(a, (double)v) : 0.0f;
-        xn[i] = o;
-        s0 += -(double)h[i] * ((double)o - (double)x[i]);
-        s1 += fabs((double)o);
-    }
-    double t = block_reduce<false>(s0, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-    t = block_reduce<false>(s1, sh);
-    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = t;
-}
-
 // Barzilai-Borwein quantities with s = xn - x and y = gn - g = -(hn - h):
 // slot 0 sum s^2, slot 1 sum s y, slot 2 max |hn| (= ||gn||_inf),
 // slot 3 sum |x| of the input x (used for tau at a warm start).
@@ -203,12 +164,97 @@ __global__ __launch_bounds__(SV_NT) void k_sv_bb(const float* __restrict__ x, co
     if (threadIdx.x == 0) part[3 * gridDim.x + blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void k_sv_fill(float* __restrict__ v, size_t n, float val) {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) v[i] = val;
+// Projection onto the l1 ball: xn = soft(v, lam), v = x + c h, with lam the
+// root of S(lam) = sum max(|v| - lam, 0) = tau, found by Newton's method
+// started at the previous projection's root (successive projections in a
+// solve have nearby roots). S is convex, decreasing and piecewise linear:
+// from below the root the iterates increase to the exact root of the final
+// active set, and a step from above lands at or below the root (a convex
+// function lies above its tangents), so at most one step is spent above.
+// One launch per step: every block writes its partial sums, and the last
+// block to finish (an atomic ticket after a memory fence) adds the partials
+// in block order and takes the step, so the result is deterministic. Steps
+// after convergence return at once. State: st[0] = lam, st[1] = done flag.
+constexpr int PJ_NT = 256;
+constexpr int PJ_BLOCKS = 256;
+constexpr int PJ_STEPS = 12;   // launches per projection; the host checks the flag
+
+__global__ __launch_bounds__(PJ_NT) void k_sv_pj_step(const float* __restrict__ x, const float* __restrict__ h,
+                                                     double c, double tau, size_t n, double* __restrict__ st,
+                                                     double* __restrict__ part, unsigned* __restrict__ ticket) {
+    __shared__ double sh[PJ_NT / 64];
+    __shared__ bool last;
+    if (st[1] != 0.0) return;   // converged in an earlier launch (uniform)
+    const double lam = st[0];
+    double s = 0.0, k = 0.0;
+    for (size_t i = (size_t)blockIdx.x * PJ_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * PJ_NT) {
+        const float v = (float)((double)x[i] + c * (double)h[i]);
+        const double a = fabs((double)v);
+        if (a > lam) { s += a - lam; k += 1.0; }
+    }
+    double t = block_reduce<false>(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    t = block_reduce<false>(k, sh);
+    if (threadIdx.x == 0) {
+        part[gridDim.x + blockIdx.x] = t;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double vs = 0.0, vk = 0.0;
+    for (int j = threadIdx.x; j < (int)gridDim.x; j += PJ_NT) {
+        vs += part[j];
+        vk += part[gridDim.x + j];
+    }
+    const double S = block_reduce<false>(vs, sh);
+    const double K = block_reduce<false>(vk, sh);
+    if (threadIdx.x == 0) {
+        *ticket = 0u;
+        if (fabs(S - tau) <= 1e-12 * tau || (lam == 0.0 && S <= tau)) st[1] = 1.0;
+        else st[0] = K > 0.0 ? fmax(0.0, lam + (S - tau) / K) : 0.0;   // K = 0: above every |v|
+    }
 }
 
-__global__ void k_sv_set(double* __restrict__ p, double val) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = val;
+// xn = soft(x + c h, st[0]); partials: slot 0 sum -h.(xn - x), slot 1 sum |xn|,
+// slot 2 the done flag (so the host sees whether the steps converged).
+__global__ __launch_bounds__(SV_NT) void k_sv_soft(const float* __restrict__ x, const float* __restrict__ h,
+                                                  double c, const double* __restrict__ st, size_t n,
+                                                  float* __restrict__ xn, double* __restrict__ part) {
+    __shared__ double sh[SV_NT / 64];
+    const double L = st[0];
+    double s0 = 0.0, s1 = 0.0;
+    for (size_t i = (size_t)blockIdx.x * SV_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * SV_NT) {
+        const float v = (float)((double)x[i] + c * (double)h[i]);
+        const double a = fabs((double)v) - L;
+        const float o = a > 0 ? (float)copysign(a, (double)v) : 0.0f;
+        xn[i] = o;
+        s0 += -(double)h[i] * ((double)o - (double)x[i]);
+        s1 += fabs((double)o);
+    }
+    double t = block_reduce<false>(s0, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    t = block_reduce<false>(s1, sh);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = t;
+    if (threadIdx.x == 0) part[2 * gridDim.x + blockIdx.x] = blockIdx.x == 0 ? st[1] : 0.0;
+}
+
+// st[1] = 0 (a new projection; st[0] keeps the previous root as the start)
+__global__ void k_sv_pj_reset(double* __restrict__ st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st[1] = 0.0;
+}
+
+__global__ void k_sv_zero(double* __restrict__ p, unsigned* __restrict__ ticket) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        p[0] = 0.0;
+        p[1] = 0.0;
+        *ticket = 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sv_fill(float* __restrict__ v, size_t n, float val) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) v[i] = val;
 }
 
 }  // namespace rn
@@ -222,6 +268,8 @@ struct SolveWork {
     float *x = nullptr, *xn = nullptr, *h = nullptr, *hn = nullptr;
     float *z = nullptr, *r = nullptr, *rn = nullptr, *bt = nullptr;
     double *m = nullptr, *ring = nullptr, *Q = nullptr, *part = nullptr, *fin = nullptr, *lam = nullptr;
+    double* pj = nullptr;          // projection step partials, 2 x PJ_BLOCKS
+    unsigned* ticket = nullptr;    // last-block ticket of the projection steps
     ~SolveWork() {
         for (void* p : allocs) (void)hipFree(p);
     }
@@ -263,6 +311,10 @@ std::vector<double> cubic_basis(int N) {
     return Q;
 }
 
+// fin slots: 0-1 residual (sum r^2, sum r.b~), 2-4 projection (g.dx, ||xn||_1,
+// converged flag), 5-8 spectral step (sum s^2, sum s.y, max |hn|, ||xn||_1)
+constexpr int FIN_RES = 0, FIN_PROJ = 2, FIN_BB = 5, FIN_COUNT = 9;
+
 struct Solver {
     radon_plan_t plan;
     const rn::Plan& p;
@@ -276,20 +328,24 @@ struct Solver {
 
     void chk(hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; }
 
-    // reduce SV_BLOCKS partials of `slots` slots into fin[0..slots) and read them
-    bool finals(int slots, unsigned ops, double* out) {
-        hipLaunchKernelGGL(rn::k_sv_final, dim3(1), dim3(rn::SV_NT), 0, st, w.part, rn::SV_BLOCKS, slots, ops, w.fin);
+    // fold SV_BLOCKS partials of `slots` slots into fin[off..off+slots) (no host wait)
+    void fold(int slots, unsigned ops, int off) {
+        hipLaunchKernelGGL(rn::k_sv_final, dim3(1), dim3(rn::SV_NT), 0, st, w.part, rn::SV_BLOCKS, slots, ops,
+                           w.fin + off);
         chk(hipGetLastError());
-        chk(hipMemcpyAsync(out, w.fin, sizeof(double) * slots, hipMemcpyDeviceToHost, st));
+    }
+    // read all fin slots back (one host wait)
+    bool read(double* out) {
+        chk(hipMemcpyAsync(out, w.fin, sizeof(double) * FIN_COUNT, hipMemcpyDeviceToHost, st));
         chk(hipStreamSynchronize(st));
         return err == hipSuccess;
     }
 
-    // r = F(b - z) (z may be null), returns sum r^2 and sum r.bt (bt may be null)
-    bool residual(const float* z, float* r, const float* bt, double* sums) {
+    // r = F(b - z) (z may be null) -> fin[0] = sum r^2, fin[1] = sum r.bt (bt may be null)
+    void residual(const float* z, float* r, const float* bt) {
         const double* ring = nullptr;
         if (filt) {
-            hipLaunchKernelGGL(rn::k_sv_colmean, dim3((p.n_det + 255) / 256), dim3(256), 0, st, b, z, p.n_views,
+            hipLaunchKernelGGL(rn::k_sv_colmean, dim3((p.n_det + 31) / 32), dim3(256), 0, st, b, z, p.n_views,
                                p.n_det, w.m);
             hipLaunchKernelGGL(rn::k_sv_ringfit, dim3(1), dim3(rn::SV_NT), 0, st, w.m, w.Q, p.n_det, w.ring);
             ring = w.ring;
@@ -297,30 +353,40 @@ struct Solver {
         hipLaunchKernelGGL(rn::k_sv_resid, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, b, z, ring, bt, p.n_views,
                            p.n_det, r, w.part);
         chk(hipGetLastError());
-        return finals(2, 0u, sums);
+        fold(2, 0u, FIN_RES);
     }
 
-    // xn = P_tau(x + c h), returns sum g.(xn - x) and ||xn||_1
-    bool project(const float* x, const float* h, double c, double tau, float* xn, double* sums) {
-        hipLaunchKernelGGL(rn::k_sv_set, dim3(1), dim3(64), 0, st, w.lam, 0.0);
-        double fin[2] = {0, 0};
-        for (int round = 0; round < 16; ++round) {
-            for (int k = 0; k < 8; ++k) {
-                hipLaunchKernelGGL(rn::k_sv_l1_partial, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, h, c, w.lam,
-                                   n2, w.part);
-                hipLaunchKernelGGL(rn::k_sv_final, dim3(1), dim3(rn::SV_NT), 0, st, w.part, rn::SV_BLOCKS, 2, 0u,
-                                   w.fin);
-                hipLaunchKernelGGL(rn::k_sv_l1_newton, dim3(1), dim3(64), 0, st, w.fin, tau, w.lam);
-            }
-            // converged when the threshold no longer moves: S <= tau (within rounding)
-            hipLaunchKernelGGL(rn::k_sv_l1_partial, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, h, c, w.lam, n2,
-                               w.part);
-            if (!finals(2, 0u, fin)) return false;
-            if (fin[0] <= tau * (1.0 + 1e-12) + 1e-300) break;
-        }
-        hipLaunchKernelGGL(rn::k_sv_soft, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, h, c, w.lam, n2, xn, w.part);
+    // xn = P_tau(x + c h) -> fin[2] = sum -h.(xn - x), fin[3] = ||xn||_1,
+    // fin[4] = 1 if the Newton steps converged (else call again with fresh = false
+    // to continue them)
+    void project(const float* x, const float* h, double c, double tau, float* xn, bool fresh = true) {
+        if (fresh) hipLaunchKernelGGL(rn::k_sv_pj_reset, dim3(1), dim3(64), 0, st, w.lam);
+        for (int k = 0; k < rn::PJ_STEPS; ++k)
+            hipLaunchKernelGGL(rn::k_sv_pj_step, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, n2, w.lam,
+                               w.pj, w.ticket);
+        hipLaunchKernelGGL(rn::k_sv_soft, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, h, c, w.lam, n2, xn,
+                           w.part);
         chk(hipGetLastError());
-        return finals(2, 0u, sums);
+        fold(3, 1u << 2, FIN_PROJ);
+    }
+
+    // spectral-step sums of s = xn - x, y = -(hn - h) -> fin[4..7] (x, h may be null)
+    void bb(const float* x, const float* xn, const float* h, const float* hn) {
+        hipLaunchKernelGGL(rn::k_sv_bb, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, xn, h, hn, n2, w.part);
+        chk(hipGetLastError());
+        fold(4, 1u << 2, FIN_BB);
+    }
+
+    // project and wait until the Newton steps have converged
+    bool project_sync(const float* x, const float* h, double c, double tau, float* xn, double* fin) {
+        bool fresh = true;
+        for (int round = 0; round < 64; ++round) {
+            project(x, h, c, tau, xn, fresh);
+            fresh = false;
+            if (!read(fin)) return false;
+            if (fin[FIN_PROJ + 2] != 0.0) return true;
+        }
+        return true;   // the last step's threshold is used
     }
 
     bool forward(const float* x, float* z) {
@@ -346,7 +412,7 @@ extern "C" radon_status_t radon_ring_filter(radon_plan_t plan, const float* y_de
     const std::vector<double> Q = cubic_basis(p.n_det);
     if (hipMemcpy(w.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice) != hipSuccess)
         return RADON_ERR_DEVICE;
-    hipLaunchKernelGGL(rn::k_sv_colmean, dim3((p.n_det + 255) / 256), dim3(256), 0, st, y_dev, nullptr, p.n_views,
+    hipLaunchKernelGGL(rn::k_sv_colmean, dim3((p.n_det + 31) / 32), dim3(256), 0, st, y_dev, nullptr, p.n_views,
                        p.n_det, w.m);
     hipLaunchKernelGGL(rn::k_sv_ringfit, dim3(1), dim3(rn::SV_NT), 0, st, w.m, w.Q, p.n_det, w.ring);
     hipLaunchKernelGGL(rn::k_sv_resid, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, y_dev, nullptr, w.ring, nullptr,
@@ -366,9 +432,11 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
     if (!w.alloc(&w.x, n2) || !w.alloc(&w.xn, n2) || !w.alloc(&w.h, n2) || !w.alloc(&w.hn, n2) ||
         !w.alloc(&w.z, ns) || !w.alloc(&w.r, ns) || !w.alloc(&w.rn, ns) || !w.alloc(&w.bt, ns) ||
         !w.alloc(&w.m, p.n_det) || !w.alloc(&w.ring, p.n_det) || !w.alloc(&w.Q, (size_t)p.n_det * 4) ||
-        !w.alloc(&w.part, (size_t)rn::SV_SLOTS * rn::SV_BLOCKS) || !w.alloc(&w.fin, rn::SV_SLOTS) ||
-        !w.alloc(&w.lam, 1))
+        !w.alloc(&w.part, (size_t)rn::SV_SLOTS * rn::SV_BLOCKS) || !w.alloc(&w.fin, FIN_COUNT) ||
+        !w.alloc(&w.lam, 2) || !w.alloc(&w.pj, (size_t)2 * rn::PJ_BLOCKS) || !w.alloc(&w.ticket, 1))
         return RADON_ERR_OOM;
+    // projection state: threshold 0 (no warm start yet), ticket 0
+    hipLaunchKernelGGL(rn::k_sv_zero, dim3(1), dim3(64), 0, (hipStream_t)stream, w.lam, w.ticket);
     hipStream_t st = (hipStream_t)stream;
     Solver S{plan, p, w, st, opts->ring_filter != 0, b_dev, n2, ns};
     const std::vector<double> Q = cubic_basis(p.n_det);
@@ -377,28 +445,27 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
     const double sigma = opts->sigma, opt_tol = opts->opt_tol, bp_tol = opts->bp_tol, dec_tol = opts->dec_tol;
     const double bb_min = 1e-16, bb_max = 1e5;   // spectral step bounds
     const int n_mem = 3;
-    double sums[4];
+    double fin[FIN_COUNT];
     // b~ = F b and its norm
-    if (!S.residual(nullptr, w.bt, nullptr, sums)) return RADON_ERR_DEVICE;
-    const double bnorm = sqrt(sums[0]);
-    // start point and tau
+    S.residual(nullptr, w.bt, nullptr);
+    if (!S.read(fin)) return RADON_ERR_DEVICE;
+    const double bnorm = sqrt(fin[FIN_RES]);
+    // start point, tau = ||x0||_1, and the projection of x0 (a no-op at that radius)
     if (opts->warm_start) S.chk(hipMemcpyAsync(w.x, x_dev, sizeof(float) * n2, hipMemcpyDeviceToDevice, st));
     else hipLaunchKernelGGL(rn::k_sv_fill, dim3(1024), dim3(256), 0, st, w.x, n2, 0.0f);
-    hipLaunchKernelGGL(rn::k_sv_bb, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, nullptr, w.x, nullptr, w.x, n2,
-                       w.part);
-    double q4[4];
-    if (!S.finals(4, 1u << 2, q4)) return RADON_ERR_DEVICE;
-    double tau = q4[3];
-    if (!S.project(w.x, w.x, 0.0, tau, w.xn, sums)) return RADON_ERR_DEVICE;
+    S.bb(nullptr, w.x, nullptr, w.x);
+    if (!S.read(fin)) return RADON_ERR_DEVICE;
+    double tau = fin[FIN_BB + 3];
+    if (!S.project_sync(w.x, w.x, 0.0, tau, w.xn, fin)) return RADON_ERR_DEVICE;
     std::swap(w.x, w.xn);
     // r = F(b - A x), h = A^T r
-    if (!S.forward(w.x, w.z) || !S.residual(w.z, w.r, w.bt, sums)) return RADON_ERR_DEVICE;
-    double f = 0.5 * sums[0], rbt = sums[1];
+    if (!S.forward(w.x, w.z)) return RADON_ERR_DEVICE;
+    S.residual(w.z, w.r, w.bt);
     if (!S.adjoint(w.r, w.h)) return RADON_ERR_DEVICE;
-    hipLaunchKernelGGL(rn::k_sv_bb, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, nullptr, w.x, nullptr, w.h, n2,
-                       w.part);
-    if (!S.finals(4, 1u << 2, q4)) return RADON_ERR_DEVICE;
-    double gnorm = q4[2];
+    S.bb(nullptr, w.x, nullptr, w.h);
+    if (!S.read(fin)) return RADON_ERR_DEVICE;
+    double f = 0.5 * fin[FIN_RES], rbt = fin[FIN_RES + 1];
+    double gnorm = fin[FIN_BB + 2];
     std::vector<double> fs(n_mem, f);
     double alpha = std::min(std::max(gnorm > 0 ? 1.0 / gnorm : 1.0, bb_min), bb_max);
     double f_old = INFINITY;
@@ -423,36 +490,43 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
             if (tau < tau_old) {
                 // the ball shrank: restart from the projected iterate with its
                 // own residual and gradient
-                if (!S.project(w.x, w.x, 0.0, tau, w.xn, sums)) return RADON_ERR_DEVICE;
+                if (!S.project_sync(w.x, w.x, 0.0, tau, w.xn, fin)) return RADON_ERR_DEVICE;
                 std::swap(w.x, w.xn);
-                if (!S.forward(w.x, w.z) || !S.residual(w.z, w.r, w.bt, sums)) return RADON_ERR_DEVICE;
-                f = 0.5 * sums[0];
-                rbt = sums[1];
+                if (!S.forward(w.x, w.z)) return RADON_ERR_DEVICE;
+                S.residual(w.z, w.r, w.bt);
                 if (!S.adjoint(w.r, w.h)) return RADON_ERR_DEVICE;
-                hipLaunchKernelGGL(rn::k_sv_bb, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, nullptr, w.x, nullptr,
-                                   w.h, n2, w.part);
-                if (!S.finals(4, 1u << 2, q4)) return RADON_ERR_DEVICE;
-                gnorm = q4[2];
+                S.bb(nullptr, w.x, nullptr, w.h);
+                if (!S.read(fin)) return RADON_ERR_DEVICE;
+                f = 0.5 * fin[FIN_RES];
+                rbt = fin[FIN_RES + 1];
+                gnorm = fin[FIN_BB + 2];
             }
             std::fill(fs.begin(), fs.end(), f);
         }
-        // spectral projected gradient step, non-monotone (GLL) backtracking
+        // spectral projected gradient step, non-monotone (GLL) backtracking; the
+        // gradient and spectral sums of each trial point are computed before the
+        // host reads the trial's objective, so an accepted step costs one wait
         const double fmax = *std::max_element(fs.begin(), fs.end());
         double step = 1.0, fn = 0, rbtn = 0;
         while (true) {
-            if (!S.project(w.x, w.h, step * alpha, tau, w.xn, sums)) return RADON_ERR_DEVICE;
-            const double gtd = sums[0];
-            if (!S.forward(w.xn, w.z) || !S.residual(w.z, w.rn, w.bt, sums)) return RADON_ERR_DEVICE;
-            fn = 0.5 * sums[0];
-            rbtn = sums[1];
+            bool fresh = true;
+            for (int round = 0; round < 64; ++round) {   // rarely more than one round
+                S.project(w.x, w.h, step * alpha, tau, w.xn, fresh);
+                fresh = false;
+                if (!S.forward(w.xn, w.z)) return RADON_ERR_DEVICE;
+                S.residual(w.z, w.rn, w.bt);
+                if (!S.adjoint(w.rn, w.hn)) return RADON_ERR_DEVICE;
+                S.bb(w.x, w.xn, w.h, w.hn);
+                if (!S.read(fin)) return RADON_ERR_DEVICE;
+                if (fin[FIN_PROJ + 2] != 0.0) break;
+            }
+            const double gtd = fin[FIN_PROJ];
+            fn = 0.5 * fin[FIN_RES];
+            rbtn = fin[FIN_RES + 1];
             if (fn <= fmax + 1e-4 * gtd || step < 1e-10) break;
             step *= 0.5;
         }
-        if (!S.adjoint(w.rn, w.hn)) return RADON_ERR_DEVICE;
-        hipLaunchKernelGGL(rn::k_sv_bb, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, w.x, w.xn, w.h, w.hn, n2,
-                           w.part);
-        if (!S.finals(4, 1u << 2, q4)) return RADON_ERR_DEVICE;
-        const double sts = q4[0], sty = q4[1];
+        const double sts = fin[FIN_BB], sty = fin[FIN_BB + 1];
         alpha = sty <= 0 ? bb_max : std::min(std::max(sts / sty, bb_min), bb_max);
         f_old = f;
         std::swap(w.x, w.xn);
@@ -460,22 +534,19 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
         std::swap(w.h, w.hn);
         f = fn;
         rbt = rbtn;
-        gnorm = q4[2];
+        gnorm = fin[FIN_BB + 2];
         fs.erase(fs.begin());
         fs.push_back(f);
     }
     if (it > opts->max_iter) it = opts->max_iter;
     // ||x||_1 of the result, then hand it back
-    hipLaunchKernelGGL(rn::k_sv_bb, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, nullptr, w.x, nullptr, w.x, n2,
-                       w.part);
-    if (!S.finals(4, 1u << 2, q4)) return RADON_ERR_DEVICE;
+    S.bb(nullptr, w.x, nullptr, w.x);
     S.chk(hipMemcpyAsync(x_dev, w.x, sizeof(float) * n2, hipMemcpyDeviceToDevice, st));
-    S.chk(hipStreamSynchronize(st));
-    if (S.err != hipSuccess) return RADON_ERR_DEVICE;
+    if (!S.read(fin)) return RADON_ERR_DEVICE;
     if (stats) {
         stats->rnorm = sqrt(2 * f);
         stats->tau = tau;
-        stats->x_l1 = q4[3];
+        stats->x_l1 = fin[FIN_BB + 3];
         stats->iterations = it;
         stats->n_forward = S.nf;
         stats->n_adjoint = S.na;
