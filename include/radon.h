@@ -280,6 +280,45 @@ typedef struct {
 radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev, float* x_dev, const radon_solve_opts* opts,
                                 radon_solve_stats* stats, void* stream);
 
+/*
+ * Learned warm start (an extension beyond the paper, which starts its solves
+ * from zero): a 4-level convolutional encoder-decoder (3x3 convolutions,
+ * 32-64-128-256 channels, ReLU, 2x2 average pooling, nearest upsampling, skip
+ * additions, a final correction added to the input) with bfloat16
+ * activations and float32 accumulation on the matrix cores, trained with
+ * Adam (beta 0.9, 0.999) on mean squared error. It maps the filtered adjoint
+ * (radon_fbp) of a sinogram to a start image for radon_solve_bpdn.
+ * Images are batch x height x width float32 on the device (height, width
+ * multiples of 8); the network's batch is fixed at creation. Initial weights:
+ * He-normal from `seed` (host RNG), the last layer zero (the network starts as
+ * the identity). All calls are stream-ordered; train_step synchronises the
+ * stream when loss_host is not NULL.
+ */
+typedef struct radon_cnn_s* radon_cnn_t;
+radon_status_t radon_cnn_create(radon_cnn_t* out, int batch, int height, int width, uint64_t seed);
+void radon_cnn_destroy(radon_cnn_t net);   /* NULL-safe */
+radon_status_t radon_cnn_forward(radon_cnn_t net, const float* in_dev, float* out_dev, void* stream);
+/* One Adam step on a batch: pred_dev receives the forward output, *loss_host
+ * (may be NULL) the mean squared error. */
+radon_status_t radon_cnn_train_step(radon_cnn_t net, const float* in_dev, const float* target_dev, float lr,
+                                    float* loss_host, float* pred_dev, void* stream);
+/* Parameters in layer order (weights Cout x Cin x 3 x 3, then biases), host
+ * float32 arrays of radon_cnn_param_count values; get_grads returns the last
+ * training step's gradients (a test hook). */
+int64_t radon_cnn_param_count(radon_cnn_t net);
+radon_status_t radon_cnn_get_params(radon_cnn_t net, float* host, int64_t n);
+radon_status_t radon_cnn_set_params(radon_cnn_t net, const float* host, int64_t n);
+radon_status_t radon_cnn_get_grads(radon_cnn_t net, float* host, int64_t n);
+/* Test hook: one 3x3 convolution (stride 1, zero padding 1) of bf16 tensors
+ * in (B x Cin x H x W) with float32 weights w (Cout x Cin x 3 x 3) and bias
+ * (may be NULL): out = [relu](conv + bias) [+ res], to out16 (bf16) and/or
+ * out32; and, for an output gradient gout (bf16), the data gradient gin (bf16)
+ * and the weight and bias gradients gw, gb (float32). NULL outputs are
+ * skipped. Synchronises the stream. */
+radon_status_t radon_cnn_conv_test(const uint16_t* in, const float* w, const float* bias, const uint16_t* res,
+                                   uint16_t* out16, float* out32, int relu, const uint16_t* gout, uint16_t* gin,
+                                   float* gw, float* gb, int B, int Cin, int Cout, int H, int W, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libradon.so")
-SOURCES = ["radon_api.hip", "radon_fwd.hip", "radon_adj.hip", "radon_solver.hip", "radon_batch.hip"]
+SOURCES = ["radon_api.hip", "radon_fwd.hip", "radon_adj.hip", "radon_solver.hip", "radon_batch.hip", "cnn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

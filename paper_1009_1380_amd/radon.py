@@ -60,6 +60,16 @@ _SIGS = {
     "radon_batch_adjoint": (_c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
     "radon_batch_graphs_recorded": (_c_int, [_vp]),
     "radon_batch_destroy": (None, [_vp]),
+    "radon_cnn_create": (_c_int, [ctypes.POINTER(_vp), _c_int, _c_int, _c_int, ctypes.c_uint64]),
+    "radon_cnn_destroy": (None, [_vp]),
+    "radon_cnn_forward": (_c_int, [_vp, _vp, _vp, _vp]),
+    "radon_cnn_train_step": (_c_int, [_vp, _vp, _vp, ctypes.c_float, ctypes.POINTER(ctypes.c_float), _vp, _vp]),
+    "radon_cnn_param_count": (_c_i64, [_vp]),
+    "radon_cnn_get_params": (_c_int, [_vp, _vp, _c_i64]),
+    "radon_cnn_set_params": (_c_int, [_vp, _vp, _c_i64]),
+    "radon_cnn_get_grads": (_c_int, [_vp, _vp, _c_i64]),
+    "radon_cnn_conv_test": (_c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c_int, _vp, _vp, _vp, _vp, _c_int, _c_int,
+                                     _c_int, _c_int, _c_int, _vp]),
 }
 
 
@@ -405,3 +415,106 @@ class Batch:
         ous = self._ptrs(outs, [(p.n, p.n) for p in self.plans], "outs")
         _check(lib().radon_batch_adjoint(self._h, ins, ous, _stream_ptr(stream)), "radon_batch_adjoint")
         return outs
+
+
+def _ptr_or_null(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+
+
+def _check_dev(t, dtype, name):
+    torch = _torch()
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor")
+
+
+class WarmStartNet:
+    """The learned warm start's encoder-decoder (radon_cnn_*): bf16 matrix-core
+    convolutions, float32 parameters and Adam state, fixed batch and size."""
+
+    def __init__(self, batch: int, height: int, width: int, seed: int = 0):
+        self.batch, self.height, self.width = int(batch), int(height), int(width)
+        h = ctypes.c_void_p()
+        _check(lib().radon_cnn_create(ctypes.byref(h), self.batch, self.height, self.width, int(seed)),
+               "radon_cnn_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().radon_cnn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _shape(self):
+        return (self.batch, self.height, self.width)
+
+    def forward(self, x, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self._shape(), dtype=torch.float32, device=x.device)
+        _check(lib().radon_cnn_forward(self._h, _dev_ptr(x, self._shape(), "x"), _dev_ptr(out, self._shape(), "out"),
+                                       _stream_ptr(stream)), "radon_cnn_forward")
+        return out
+
+    def train_step(self, x, target, lr: float, pred=None, stream=None) -> float:
+        torch = _torch()
+        if pred is None:
+            pred = torch.empty(self._shape(), dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        _check(lib().radon_cnn_train_step(self._h, _dev_ptr(x, self._shape(), "x"),
+                                          _dev_ptr(target, self._shape(), "target"), float(lr), ctypes.byref(loss),
+                                          _dev_ptr(pred, self._shape(), "pred"), _stream_ptr(stream)),
+               "radon_cnn_train_step")
+        return float(loss.value)
+
+    def param_count(self) -> int:
+        return int(lib().radon_cnn_param_count(self._h))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.param_count(), dtype=np.float32)
+        _check(lib().radon_cnn_get_params(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size), "radon_cnn_get_params")
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if a.size != self.param_count():
+            raise ValueError(f"need {self.param_count()} parameters, got {a.size}")
+        _check(lib().radon_cnn_set_params(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size), "radon_cnn_set_params")
+
+    def get_grads(self) -> np.ndarray:
+        a = np.empty(self.param_count(), dtype=np.float32)
+        _check(lib().radon_cnn_get_grads(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size), "radon_cnn_get_grads")
+        return a
+
+
+def cnn_conv_test(x16, w, bias=None, res16=None, relu=False, gout16=None, want_out16=False, stream=None):
+    """Test hook over radon_cnn_conv_test: bf16 tensors are torch.int16 views of
+    bfloat16 bits (B, C, H, W); w float32 (Cout, Cin, 3, 3) on the device.
+    Returns (out32, out16 or None, gin16 or None, gw, gb)."""
+    torch = _torch()
+    B, Cin, H, W = (int(v) for v in x16.shape)
+    Cout = int(w.shape[0])
+    _check_dev(x16, torch.int16, "x16")
+    _check_dev(w, torch.float32, "w")
+    _check_dev(bias, torch.float32, "bias")
+    _check_dev(res16, torch.int16, "res16")
+    _check_dev(gout16, torch.int16, "gout16")
+    dev = x16.device
+    out32 = torch.empty((B, Cout, H, W), dtype=torch.float32, device=dev)
+    out16 = torch.empty((B, Cout, H, W), dtype=torch.int16, device=dev) if want_out16 else None
+    gin = gw = gb = None
+    if gout16 is not None:
+        gin = torch.empty((B, Cin, H, W), dtype=torch.int16, device=dev)
+        gw = torch.empty((Cout, Cin, 3, 3), dtype=torch.float32, device=dev)
+        gb = torch.empty((Cout,), dtype=torch.float32, device=dev)
+    _check(lib().radon_cnn_conv_test(_ptr_or_null(x16), _ptr_or_null(w), _ptr_or_null(bias), _ptr_or_null(res16),
+                                     _ptr_or_null(out16), _ptr_or_null(out32), int(bool(relu)), _ptr_or_null(gout16),
+                                     _ptr_or_null(gin), _ptr_or_null(gw), _ptr_or_null(gb), B, Cin, Cout, H, W,
+                                     _stream_ptr(stream)), "radon_cnn_conv_test")
+    return out32, out16, gin, gw, gb

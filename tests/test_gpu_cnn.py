@@ -1,0 +1,136 @@
+"""Warm-start network kernels and network against the float64 reference.
+
+The GPU computes with bfloat16 activations and float32 accumulation; the
+references get the same bfloat16-rounded inputs and weights, so a single
+convolution agrees to float32 accumulation error, and the whole network to
+the bfloat16 rounding of its intermediate activations.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import torch.nn.functional as Fn  # noqa: E402
+
+from oracle.cnn import forward as ref_forward, loss_and_grads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1009_1380_amd import WarmStartNet, cnn_conv_test  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def bf16_bits(a):
+    """float array -> (bfloat16-rounded float64 array, int16 device tensor of its bits)."""
+    t = torch.as_tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16)
+    return t.double().numpy(), t.view(torch.int16).to(DEV)
+
+
+def from_bits(t16):
+    return t16.cpu().view(torch.bfloat16).double().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("B,Cin,Cout,H,W", [(2, 1, 32, 16, 16), (2, 32, 64, 12, 20), (1, 128, 256, 8, 8),
+                                            (2, 32, 1, 16, 24), (1, 3, 5, 7, 9)])
+def test_conv_forward_and_gradients(B, Cin, Cout, H, W):
+    note(f"conv B={B} Cin={Cin} Cout={Cout} H={H} W={W}")
+    rng = np.random.default_rng(B * 1000 + Cin + Cout)
+    x, x16 = bf16_bits(rng.standard_normal((B, Cin, H, W)))
+    w, _ = bf16_bits(rng.standard_normal((Cout, Cin, 3, 3)) / np.sqrt(Cin * 9))
+    bias = rng.standard_normal(Cout)
+    r, r16 = bf16_bits(rng.standard_normal((B, Cout, H, W)))
+    g, g16 = bf16_bits(rng.standard_normal((B, Cout, H, W)))
+    wd = torch.as_tensor(w, dtype=torch.float32).to(DEV)
+    bd = torch.as_tensor(bias, dtype=torch.float32).to(DEV)
+    # reference in float64 with autograd
+    xt = torch.as_tensor(x).requires_grad_(True)
+    wt = torch.as_tensor(w).requires_grad_(True)
+    bt = torch.as_tensor(bias.astype(np.float32).astype(np.float64)).requires_grad_(True)
+    conv = Fn.conv2d(xt, wt, bt, padding=1)
+    conv.backward(torch.as_tensor(g))
+    ref = (torch.relu(conv) + torch.as_tensor(r)).detach().numpy()
+    out32, out16, gin, gw, gb = cnn_conv_test(x16, wd, bd, r16, relu=True, gout16=g16, want_out16=True)
+    assert rel(out32.cpu().numpy(), ref) <= 1e-5
+    assert np.max(np.abs(from_bits(out16) - out32.cpu().double().numpy())) <= 2 ** -7 * np.abs(ref).max()
+    assert rel(gw.cpu().numpy(), wt.grad.numpy()) <= 1e-5
+    assert rel(gb.cpu().numpy(), bt.grad.numpy()) <= 1e-5
+    assert rel(from_bits(gin), xt.grad.numpy()) <= 1e-2      # bf16 output
+    # plain convolution (no bias, no ReLU, no residual)
+    out32b, _, _, _, _ = cnn_conv_test(x16, wd)
+    assert rel(out32b.cpu().numpy(), Fn.conv2d(torch.as_tensor(x), torch.as_tensor(w), padding=1).numpy()) <= 1e-5
+
+
+def _random_params(net, scale_last=0.05, seed=0):
+    from oracle.cnn import CHANNELS
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k, (ci, co) in enumerate(CHANNELS):
+        s = np.sqrt(2.0 / (ci * 9)) * (scale_last if k == len(CHANNELS) - 1 else 1.0)
+        parts.append(s * rng.standard_normal(co * ci * 9))
+        parts.append(0.01 * rng.standard_normal(co))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == net.param_count()
+    return p
+
+
+def test_network_forward_and_gradients_vs_reference():
+    note("network forward/backward vs reference")
+    B, H, W = 2, 32, 48
+    net = WarmStartNet(B, H, W, seed=3)
+    p = _random_params(net, scale_last=1.0, seed=4)
+    net.set_params(p)
+    assert np.array_equal(net.get_params(), p)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((B, H, W)).astype(np.float32)
+    t = rng.standard_normal((B, H, W)).astype(np.float32)
+    xd, td = torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)
+    y = net.forward(xd).cpu().numpy()
+    yref = ref_forward(p, x)
+    assert rel(y - x, yref - x) <= 5e-2          # the network's correction, through bf16 activations
+    loss = net.train_step(xd, td, 0.0)           # lr = 0: gradients only
+    lref, gref = loss_and_grads(p, x, t)
+    assert abs(loss - lref) <= 1e-2 * lref
+    g = net.get_grads()
+    off = 0
+    from oracle.cnn import CHANNELS
+    for ci, co in CHANNELS:
+        nw = co * ci * 9
+        assert rel(g[off:off + nw], gref[off:off + nw]) <= 5e-2, (ci, co)
+        off += nw + co
+    assert np.array_equal(net.get_params(), p)   # lr = 0 left the parameters alone
+
+
+def test_training_reduces_loss_and_is_deterministic():
+    note("network training")
+    B, H, W = 4, 32, 32
+    rng = np.random.default_rng(6)
+    xs = rng.standard_normal((8, B, H, W)).astype(np.float32)
+    # target: a fixed smoothing of the input (learnable by the network)
+    k = torch.tensor([[1, 2, 1], [2, 4, 2], [1, 2, 1]], dtype=torch.float32) / 16
+    ts = Fn.conv2d(torch.from_numpy(xs.reshape(-1, 1, H, W)), k[None, None], padding=1).numpy().reshape(xs.shape)
+    losses = []
+    for run in range(2):
+        net = WarmStartNet(B, H, W, seed=7)
+        ls = [net.train_step(torch.from_numpy(xs[i % 8]).to(DEV), torch.from_numpy(ts[i % 8]).to(DEV), 2e-3)
+              for i in range(60)]
+        losses.append(ls)
+        params = net.get_params()
+        if run == 0:
+            p0 = params
+    assert losses[0] == losses[1] and np.array_equal(p0, params)
+    assert np.mean(losses[0][-8:]) < 0.3 * np.mean(losses[0][:8])
