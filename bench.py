@@ -235,6 +235,33 @@ def batch_times(dev, n_slices: int = 64, repeats: int = 5, seed: int = 0):
     }
 
 
+def warmstart_times(pairs: int = 256, epochs: int = 4, n_eval: int = 20):
+    """Learned warm start on the 512^2, 90-view workload, reduced so the bench
+    stays short (the full 2000-pair run is paper_1009_1380_amd.warmstart):
+    pairs generated by the method, training, cold vs warm on held-out seeds."""
+    import torch
+
+    from paper_1009_1380_amd import WarmStartNet
+    from paper_1009_1380_amd.warmstart import Problem, evaluate, generate_pairs, summarize, train
+
+    prob = Problem(512, 90)
+    t0 = time.perf_counter()
+    xs, ts = generate_pairs(prob, range(pairs))
+    net = WarmStartNet(8, 512, 512, seed=0)
+    hist = train(net, xs, ts, epochs, 1e-3)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    net1 = WarmStartNet(1, 512, 512, seed=0)
+    net1.set_params(net.get_params())
+    rows = evaluate(prob, net1, range(10_000_000, 10_000_000 + n_eval))
+    out = {"workload": f"512^2 random-disk slices, 90 views x 512 bins, 30 dB noise + ring gains; {pairs} "
+                       f"method-generated training pairs, {epochs} epochs, {n_eval} held-out slices; basis pursuit to "
+                       f"relative residual error 1e-3; warm time includes filtered adjoint + network",
+           "prepare_seconds": round(t_prep, 1), "final_loss": hist[-1]}
+    out.update({k: (round(v, 4) if isinstance(v, float) else v) for k, v in summarize(rows).items()})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +271,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the reduced-view solve timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-slice batch timing")
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -387,6 +415,9 @@ def main():
     if not args.no_batch:
         print("bench: timing the uneven-slice batch", file=sys.stderr, flush=True)
         line["batch"] = batch_times(dev)
+    if not args.no_warmstart:
+        print("bench: learned warm start (reduced)", file=sys.stderr, flush=True)
+        line["warmstart"] = warmstart_times()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_views)
