@@ -17,6 +17,21 @@
 
 namespace rn {
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, then for every wave. __syncthreads() also waits for the
+// wave's outstanding global loads and stores, which exposes their latency at
+// every barrier; global data is waited for where it is used instead.
+#ifndef RN_LDS_SYNC
+#define RN_LDS_SYNC 1
+#endif
+__device__ __forceinline__ void lds_sync() {
+#if RN_LDS_SYNC
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+#else
+    __syncthreads();
+#endif
+}
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -174,7 +189,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             for (int m = 0; m < R; ++m) v[it][m] = src[lds_pad(bf + m * NB)];
         }
     }
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int b = tid + it * NT;
@@ -197,7 +212,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             for (int m = 0; m < R; ++m) dst[lds_pad(o + m * L)] = v[it][m];
         }
     }
-    __syncthreads();
+    lds_sync();
 }
 
 template <int LEN, int P, int L, int B, int NT, int LS>
@@ -308,7 +323,7 @@ __device__ __forceinline__ void fft_regs(float2 (&v)[I0][R0], float2* buf, const
     using IO = FftRegIO<LEN, B, NT>;
     static_assert(IO::NP >= 2, "register form needs at least two passes");
     fft_first_from_regs<LEN, B, NT>(v, buf, tid);
-    __syncthreads();
+    lds_sync();
     fft_mid_passes<LEN, 1, IO::R0, B, NT, IO::LS>(buf, tw, tid);
     fft_last_to_regs<LEN, B, NT>(buf, tw, tid, out);
 }
@@ -326,6 +341,9 @@ constexpr int line_threads(int len) { return len >= 1024 ? 512 : (len >= 256 ? 2
 #ifndef RN_COL_NT
 #define RN_COL_NT 512
 #endif
+#ifndef RN_RAY_NT
+#define RN_RAY_NT 512
+#endif
 constexpr int row_threads(int len) { return len >= 1024 ? RN_ROW_NT : line_threads(len); }
 constexpr int col_threads(int len) { return len >= 1024 ? RN_COL_NT : line_threads(len); }
 
@@ -333,5 +351,9 @@ constexpr int fft_threads(int len, int b) {
     int work = len * b / 8;
     return work >= 1024 ? 512 : (work >= 256 ? 256 : (work >= 128 ? 128 : 64));
 }
+// Threads of the ray kernels (F4, A1: two rays of length len per workgroup).
+// These launches hold only n_views/2 workgroups, so long rays get more
+// threads than their butterfly count asks for: more waves in flight per CU.
+constexpr int ray_threads(int len) { return len >= 2048 ? RN_RAY_NT : fft_threads(len, 1); }
 
 }  // namespace rn

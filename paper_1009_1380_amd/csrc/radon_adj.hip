@@ -11,7 +11,7 @@ hipError_t launch_a1(const Plan& p, const float* sino, bool filtered, hipStream_
     switch (p.n_det) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = fft_threads(L, 1);                                                  \
+        constexpr int NT = ray_threads(L);                                                     \
         hipLaunchKernelGGL((k_a1_rays<L, NT>), grid, dim3(NT), 0, st, sino, p.Yh, p.tw_N, wq,   \
                            p.n_views);                                                         \
         break;                                                                                 \

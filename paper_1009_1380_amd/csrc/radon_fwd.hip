@@ -102,7 +102,7 @@ hipError_t launch_f4(const Plan& p, float* sino, hipStream_t st) {
     switch (p.n_det) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
-        constexpr int NT = fft_threads(L, 1);                                                  \
+        constexpr int NT = ray_threads(L);                                                     \
         hipLaunchKernelGGL((k_f4_rays<L, NT>), grid, dim3(NT), 0, st, p.Xr, sino, p.tw_N,       \
                            p.n_views);                                                         \
         break;                                                                                 \

@@ -128,69 +128,82 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // ---------------------------------------------------------------- F1
-// Four image rows per workgroup, as two packed pairs done one after the other
-// (LDS holds one pair: lines r = 0 and r = 1). Row i holds py = i - n/2,
-// column j holds px = j - n/2 (stored at px mod n in the length-n FFT). The
-// four outputs of each frequency mx are kept in registers and written to
-// T1[mx][i0..i0+3] together (32 contiguous bytes).
+// Four image rows per workgroup, packed as two complex lines z_p = row 2p +
+// i row 2p+1 (p = 0, 1). Row i holds py = i - n/2, column j holds px = j - n/2
+// (stored at px mod n in the length-n FFT). The even frequencies mx = 2k are
+// the length-n FFT of z_p, the odd ones mx = 2k+1 that of z_p e^{-i pi px/n};
+// the two line pairs are transformed one after the other, and each
+// frequency's four outputs are written to T1[mx][i0..i0+3] (32 contiguous
+// bytes) straight from LDS. Only the deapodized inputs wait in registers.
+// Waves per SIMD the row kernels are compiled for: with 1024 threads, 8
+// holds two workgroups on a CU (at most 64 VGPRs per lane), which lines of up
+// to 2560 points fit without spilling.
+constexpr int row_waves(int len) { return len <= 2560 ? 8 : 4; }
+
 template <int NL, int NT>
-__global__ __launch_bounds__(NT) void k_f1_rows(const float* __restrict__ img, float2* __restrict__ T1,
+__device__ __forceinline__ void f1_store(float2* __restrict__ T1, const float2* lds, int m, int k, int kc, int i0) {
+    constexpr int LS = lds_ls(NL);
+    float2 o[4];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const float2 zk = lds[p * LS + lds_pad(k)];
+        const float2 zc = cconj(lds[p * LS + lds_pad(kc)]);
+        const float2 sm = cadd(zk, zc), df = csub(zk, zc);
+        o[2 * p] = make_float2(0.5f * sm.x, 0.5f * sm.y);
+        o[2 * p + 1] = make_float2(0.5f * df.y, -0.5f * df.x);   // (zk - zc) / 2i
+    }
+    float2* dst = T1 + (size_t)m * NL + i0;
+    if (i0 + 1 < NL) *reinterpret_cast<float4*>(dst) = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
+    if (i0 + 3 < NL) *reinterpret_cast<float4*>(dst + 2) = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+}
+
+template <int NL, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL)))) void k_f1_rows(const float* __restrict__ img, float2* __restrict__ T1,
                                                const float* __restrict__ psi_inv,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
     constexpr int LS = lds_ls(NL);
-    constexpr int PM = (NL + 1 + NT - 1) / NT;   // frequencies mx per thread
+    constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
     __shared__ float2 lds[2 * LS];
     const int tid = threadIdx.x;
     const int i0 = 4 * xcd_block(blockIdx.x, gridDim.x);
-    float2 out[PM][4];
+    float2 z[PJ][2];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        const int r0 = i0 + 2 * p;
-        for (int j = tid; j < NL; j += NT) {
+    for (int c = 0; c < PJ; ++c) {
+        const int j = tid + c * NT;
+        float r[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r[q] = (j < NL && i0 + q < NL) ? img[(size_t)(i0 + q) * NL + j] : 0.f;
+        if (j < NL) {
             const float pj = psi_inv[j];
-            float a = 0.f, b = 0.f;
-            if (r0 < NL) a = img[(size_t)r0 * NL + j] * psi_inv[r0] * pj;
-            if (r0 + 1 < NL) b = img[(size_t)(r0 + 1) * NL + j] * psi_inv[r0 + 1] * pj;
             const int pos = lds_pad((j + NL / 2) % NL);
-            const float2 z = make_float2(a, b);
-            lds[pos] = z;
-            lds[LS + pos] = cmul(z, shift[j]);
-        }
-        __syncthreads();
-        fft_lds<NL, 2, NT>(lds, tw, tid);
 #pragma unroll
-        for (int c = 0; c < PM; ++c) {
-            const int m = tid + c * NT;
-            if (m <= NL) {
-                float2 zk, zc;
-                if ((m & 1) == 0) {
-                    const int k = m >> 1;
-                    zk = lds[lds_pad(k)];
-                    zc = cconj(lds[lds_pad((NL - k) % NL)]);
-                } else {
-                    const int k = m >> 1;
-                    zk = lds[LS + lds_pad(k)];
-                    zc = cconj(lds[LS + lds_pad(NL - 1 - k)]);
-                }
-                const float2 sm = cadd(zk, zc), df = csub(zk, zc);
-                out[c][2 * p] = make_float2(0.5f * sm.x, 0.5f * sm.y);
-                out[c][2 * p + 1] = make_float2(0.5f * df.y, -0.5f * df.x);   // (zk - zc) / 2i
+            for (int p = 0; p < 2; ++p) {
+                const int r0 = i0 + 2 * p;
+                const float sa = r0 < NL ? psi_inv[r0] : 0.f;
+                const float sb = r0 + 1 < NL ? psi_inv[r0 + 1] : 0.f;
+                z[c][p] = make_float2(r[2 * p] * sa * pj, r[2 * p + 1] * sb * pj);
+                lds[p * LS + pos] = z[c][p];
             }
         }
-        __syncthreads();
     }
+    lds_sync();
+    fft_lds<NL, 2, NT>(lds, tw, tid);
+    for (int k = tid; k <= NL / 2; k += NT) f1_store<NL, NT>(T1, lds, 2 * k, k, (NL - k) % NL, i0);
+    lds_sync();
 #pragma unroll
-    for (int c = 0; c < PM; ++c) {
-        const int m = tid + c * NT;
-        if (m <= NL) {
-            float2* dst = T1 + (size_t)m * NL + i0;
-            if (i0 + 1 < NL)
-                *reinterpret_cast<float4*>(dst) = make_float4(out[c][0].x, out[c][0].y, out[c][1].x, out[c][1].y);
-            if (i0 + 3 < NL)
-                *reinterpret_cast<float4*>(dst + 2) = make_float4(out[c][2].x, out[c][2].y, out[c][3].x, out[c][3].y);
+    for (int c = 0; c < PJ; ++c) {
+        const int j = tid + c * NT;
+        if (j < NL) {
+            const int pos = lds_pad((j + NL / 2) % NL);
+            const float2 sh = shift[j];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) lds[p * LS + pos] = cmul(z[c][p], sh);
         }
     }
+    lds_sync();
+    fft_lds<NL, 2, NT>(lds, tw, tid);
+    for (int k = tid; k < NL / 2; k += NT) f1_store<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0);
 }
 
 // ---------------------------------------------------------------- F2
@@ -226,7 +239,7 @@ __global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, f
             }
         }
         fft_regs<NL, 1, NT>(v, lds, tw, tid, X0);
-        __syncthreads();
+        lds_sync();
 #pragma unroll
         for (int it = 0; it < IO::IT0; ++it) {
             const int b = tid + it * NT;
@@ -259,20 +272,20 @@ __global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, f
                 lds[lds_pad((i + NL / 2) % NL)] = c[e];
             }
         }
-        __syncthreads();
+        lds_sync();
         fft_lds<NL, 1, NT>(lds, tw, tid);
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
             const int k = tid + e * NT;
             if (k < NL) z0[e] = lds[lds_pad(k)];
         }
-        __syncthreads();
+        lds_sync();
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
             const int i = tid + e * NT;
             if (i < NL) lds[lds_pad((i + NL / 2) % NL)] = cmul(c[e], shift[i]);
         }
-        __syncthreads();
+        lds_sync();
         fft_lds<NL, 1, NT>(lds, tw, tid);
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
@@ -400,7 +413,7 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const F3Item it = items[i];
         const int x0 = it.cx * T, y0 = it.cy * T;
-        __syncthreads();   // the previous item's samples are done with the tile
+        lds_sync();   // the previous item's samples are done with the tile
         // stage the region; points with mx < 0 hold the conjugate of their mirror
 #pragma unroll
         for (int k = 0; k < PE; ++k) {
@@ -416,7 +429,7 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
                 tile[e] = make_float2(g.x, mirror ? -g.y : g.y);
             }
         }
-        __syncthreads();
+        lds_sync();
         const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
         const int b0 = it.cy * ntl + it.cx, b1 = it.cy * ntl + cx1, b2 = cy1 * ntl + it.cx, b3 = cy1 * ntl + cx1;
         const int s0 = offs4[4 * b0], n0 = offs4[4 * b0 + 4] - s0;
@@ -490,7 +503,7 @@ __global__ __launch_bounds__(NT) void k_f4_rays(const float2* __restrict__ Xr, f
         }
         lds[lds_pad(q)] = make_float2(A.x - B.y, -(A.y + B.x));
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<ND, 1, NT>(lds, tw, tid);
     const float inv = 1.0f / (float)ND;
     for (int d = tid; d < ND; d += NT) {
@@ -519,7 +532,7 @@ __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, 
         const float yb = (a0 + 1 < n_views) ? sino[(size_t)(a0 + 1) * ND + d] : 0.f;
         lds[lds_pad((d + ND / 2) % ND)] = make_float2(ya, yb);
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<ND, 1, NT>(lds, tw, tid);
     const float sc = 0.5f / (float)ND;
     for (int q = tid; q < HQ; q += NT) {
@@ -583,7 +596,7 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
 
     for (int e = tid; e < P * P; e += A2_NT) acc[e] = 0ull;
     for (int e = tid; e < NKB; e += A2_NT) kbt[e] = kbc[e];
-    __syncthreads();
+    lds_sync();
 
     const int xl = (it.cx + ntl - 1) % ntl, yu = (it.cy + ntl - 1) % ntl;
     const int b_ul = yu * ntl + xl, b_u = yu * ntl + it.cx, b_l = it.cy * ntl + xl, b_o = it.cy * ntl + it.cx;
@@ -634,7 +647,7 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) mx_abs = fmaxf(mx_abs, __shfl_xor(mx_abs, off));
     if ((tid & 63) == 0) wmax[tid >> 6] = mx_abs;
-    __syncthreads();
+    lds_sync();
     float m = wmax[0];
 #pragma unroll
     for (int w = 1; w < A2_NT / 64; ++w) m = fmaxf(m, wmax[w]);
@@ -659,7 +672,7 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
             }
         }
     }
-    __syncthreads();
+    lds_sync();
     // write out: local (lx, ly) -> mx = (x0 + lx - G/2) mod G, my = (y0 + ly - G/2) mod G
     const int xvalid = (it.cx == 0) ? 1 : T;   // tile column 0 holds only mx = G/2
     const int my0 = mod_pos(y0 - G / 2, G);
@@ -744,7 +757,7 @@ __global__ __launch_bounds__(NT) void k_a3_cols(const float2* __restrict__ grid,
             }
         }
         fft_regs<NL, 1, NT>(ve, lds, tw, tid, E);
-        __syncthreads();
+        lds_sync();
         fft_regs<NL, 1, NT>(vo, lds, tw, tid, O);
         // FFT position q is row p = q (mod n), stored at i = (q + n/2) mod n
 #pragma unroll
@@ -770,20 +783,20 @@ __global__ __launch_bounds__(NT) void k_a3_cols(const float2* __restrict__ grid,
                 odd[e] = make_float2(v.z, -v.w);
             }
         }
-        __syncthreads();
+        lds_sync();
         fft_lds<NL, 1, NT>(lds, tw, tid);
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
             const int i = tid + e * NT;
             if (i < NL) ev[e] = cconj(lds[lds_pad((i + NL / 2) % NL)]);
         }
-        __syncthreads();
+        lds_sync();
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
             const int k = tid + e * NT;
             if (k < NL) lds[lds_pad(k)] = odd[e];
         }
-        __syncthreads();
+        lds_sync();
         fft_lds<NL, 1, NT>(lds, tw, tid);
 #pragma unroll
         for (int e = 0; e < PE; ++e) {
@@ -797,71 +810,84 @@ __global__ __launch_bounds__(NT) void k_a3_cols(const float2* __restrict__ grid,
 }
 
 // ---------------------------------------------------------------- A4
-// Four image rows per workgroup (two packed pairs, one after the other):
-// complex-to-real inverse FFT along mx of T1[mx][i], mx = 0..n (Hermitian
-// extension to G points), keep px = -n/2..n/2-1, deapodize. The four inputs
-// of each mx are read together (32 contiguous bytes) and wait in registers.
+// Four image rows per workgroup: complex-to-real inverse FFT along mx of
+// T1[mx][i], mx = 0..n (Hermitian extension to G points), keep px =
+// -n/2..n/2-1, deapodize. Rows 2p and 2p+1 are packed as one complex line
+// (X_2p + i X_{2p+1}); its even positions mx = 2k form the length-n line E_p
+// and its odd ones the line O_p, and the pixel is E_p(px) + e^{+i pi px/n}
+// O_p(px). The E lines of both pairs are transformed first (their results
+// wait in registers), then the O lines; each T1[mx][i0..i0+3] (32 contiguous
+// bytes) is read once, by the pass of its parity.
 template <int NL, int NT>
-__global__ __launch_bounds__(NT) void k_a4_rows(const float2* __restrict__ T1, float* __restrict__ img,
+__device__ __forceinline__ void a4_load(const float2* __restrict__ T1, float2* lds, int m, int pk, int pc, int i0) {
+    constexpr int LS = lds_ls(NL);
+    const float2* src = T1 + (size_t)m * NL + i0;
+    const float4 v01 = *reinterpret_cast<const float4*>(src);
+    float4 v23 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i0 + 3 < NL) v23 = *reinterpret_cast<const float4*>(src + 2);
+    float2 X[4] = {make_float2(v01.x, v01.y), make_float2(v01.z, v01.w), make_float2(v23.x, v23.y),
+                   make_float2(v23.z, v23.w)};
+    if (m == 0 || m == NL) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) X[q].y = 0.f;
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const float2 X1 = X[2 * p], X2 = X[2 * p + 1];
+        const float2 z = make_float2(X1.x - X2.y, X1.y + X2.x);             // X1 + i X2
+        lds[p * LS + lds_pad(pk)] = cconj(z);                               // conjugated for the inverse
+        if (m >= 1 && m <= NL - 1) {
+            const float2 zm = make_float2(X1.x + X2.y, -X1.y + X2.x);       // conj X1 + i conj X2 at 2n - m
+            lds[p * LS + lds_pad(pc)] = cconj(zm);
+        }
+    }
+}
+
+template <int NL, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL)))) void k_a4_rows(const float2* __restrict__ T1, float* __restrict__ img,
                                                const float* __restrict__ psi_inv,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
     constexpr int LS = lds_ls(NL);
-    constexpr int PM = (NL + 1 + NT - 1) / NT;
+    constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
     __shared__ float2 lds[2 * LS];
     const int tid = threadIdx.x;
     const int i0 = 4 * xcd_block(blockIdx.x, gridDim.x);
-    float2 X[PM][4];
+    // even mx = 2k: position k, mirror 2n - 2k at n - k
+    for (int k = tid; k <= NL / 2; k += NT) a4_load<NL, NT>(T1, lds, 2 * k, k, NL - k, i0);
+    lds_sync();
+    fft_lds<NL, 2, NT>(lds, tw, tid);
+    float2 e[PJ][2];
 #pragma unroll
-    for (int c = 0; c < PM; ++c) {
-        const int m = tid + c * NT;
-        if (m <= NL) {
-            const float2* src = T1 + (size_t)m * NL + i0;
-            const float4 v01 = *reinterpret_cast<const float4*>(src);
-            X[c][0] = make_float2(v01.x, v01.y);
-            X[c][1] = make_float2(v01.z, v01.w);
-            if (i0 + 3 < NL) {
-                const float4 v23 = *reinterpret_cast<const float4*>(src + 2);
-                X[c][2] = make_float2(v23.x, v23.y);
-                X[c][3] = make_float2(v23.z, v23.w);
-            } else {
-                X[c][2] = X[c][3] = make_float2(0.f, 0.f);
-            }
+    for (int c = 0; c < PJ; ++c) {
+        const int j = tid + c * NT;
+        if (j < NL) {
+            const int pos = lds_pad((j + NL / 2) % NL);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) e[c][p] = cconj(lds[p * LS + pos]);
         }
     }
+    lds_sync();
+    // odd mx = 2k+1: position k, mirror 2n - 2k - 1 at n - 1 - k
+    for (int k = tid; k < NL / 2; k += NT) a4_load<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0);
+    lds_sync();
+    fft_lds<NL, 2, NT>(lds, tw, tid);
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        float2* even = lds;
-        float2* odd = lds + LS;
+    for (int c = 0; c < PJ; ++c) {
+        const int j = tid + c * NT;
+        if (j < NL) {
+            const int pos = lds_pad((j + NL / 2) % NL);
+            const float2 sh = cconj(shift[j]);
+            const float pj = psi_inv[j];
 #pragma unroll
-        for (int c = 0; c < PM; ++c) {
-            const int m = tid + c * NT;
-            if (m <= NL) {
-                float2 X1 = X[c][2 * p], X2 = X[c][2 * p + 1];
-                if (m == 0 || m == NL) { X1.y = 0.f; X2.y = 0.f; }
-                const float2 z = make_float2(X1.x - X2.y, X1.y + X2.x);          // X1 + i X2
-                // position m, stored conjugated for the inverse
-                if ((m & 1) == 0) even[lds_pad(m >> 1)] = cconj(z); else odd[lds_pad(m >> 1)] = cconj(z);
-                if (m >= 1 && m <= NL - 1) {
-                    const int mm = 2 * NL - m;
-                    const float2 zm = make_float2(X1.x + X2.y, -X1.y + X2.x);    // conj X1 + i conj X2
-                    if ((mm & 1) == 0) even[lds_pad(mm >> 1)] = cconj(zm); else odd[lds_pad(mm >> 1)] = cconj(zm);
-                }
+            for (int p = 0; p < 2; ++p) {
+                const float2 o = cconj(lds[p * LS + pos]);
+                const float2 zz = cadd(e[c][p], cmul(sh, o));
+                const int r0 = i0 + 2 * p;
+                if (r0 < NL) img[(size_t)r0 * NL + j] = zz.x * psi_inv[r0] * pj;
+                if (r0 + 1 < NL) img[(size_t)(r0 + 1) * NL + j] = zz.y * psi_inv[r0 + 1] * pj;
             }
         }
-        __syncthreads();
-        fft_lds<NL, 2, NT>(lds, tw, tid);
-        const int r0 = i0 + 2 * p;
-        for (int j = tid; j < NL; j += NT) {
-            const int pos = lds_pad((j + NL / 2) % NL);
-            const float2 e = cconj(lds[pos]);
-            const float2 o = cconj(lds[LS + pos]);
-            const float2 z = cadd(e, cmul(cconj(shift[j]), o));
-            const float pj = psi_inv[j];
-            if (r0 < NL) img[(size_t)r0 * NL + j] = z.x * psi_inv[r0] * pj;
-            if (r0 + 1 < NL) img[(size_t)(r0 + 1) * NL + j] = z.y * psi_inv[r0 + 1] * pj;
-        }
-        __syncthreads();
     }
 }
 
@@ -876,7 +902,7 @@ __global__ __launch_bounds__(NT) void k_fft_test(const float2* __restrict__ in, 
         float2 v = in[base + i];
         lds[lds_pad(i)] = inverse ? cconj(v) : v;
     }
-    __syncthreads();
+    lds_sync();
     fft_lds<LEN, 1, NT>(lds, tw, tid);
     for (int i = tid; i < LEN; i += NT) {
         float2 v = lds[lds_pad(i)];
