@@ -28,7 +28,7 @@ template <int W, int T>
 static hipError_t launch_a2_wt(const Plan& p, hipStream_t st) {
     if (p.n_items == 0) return hipSuccess;
     hipLaunchKernelGGL((k_a2_spread<W, T>), dim3(p.n_items), dim3(A2_NT), 0, st, p.items, p.offs4,
-                       p.recs, p.Yh, p.kbc, p.kbS, p.grid, p.partials, p.G);
+                       p.recs, p.Yh, p.kbc, p.grid, p.partials, p.G);
     return hipGetLastError();
 }
 
@@ -54,9 +54,9 @@ hipError_t launch_a2(const Plan& p, hipStream_t st) {
 hipError_t launch_a2_reduce(const Plan& p, hipStream_t st) {
     if (p.n_splits == 0) return hipSuccess;
     switch (p.T) {
-        case 8: hipLaunchKernelGGL((k_a2_reduce<8>), dim3(p.n_splits, (8 * 8 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
-        case 16: hipLaunchKernelGGL((k_a2_reduce<16>), dim3(p.n_splits, (16 * 16 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
-        case 32: hipLaunchKernelGGL((k_a2_reduce<32>), dim3(p.n_splits, (32 * 32 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
+        case 8: hipLaunchKernelGGL((k_a2_reduce<8>), dim3(p.n_splits, (A2_GX * 8 * 8 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
+        case 16: hipLaunchKernelGGL((k_a2_reduce<16>), dim3(p.n_splits, (A2_GX * 16 * 16 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
+        case 32: hipLaunchKernelGGL((k_a2_reduce<32>), dim3(p.n_splits, (A2_GX * 32 * 32 + 255) / 256), dim3(256), 0, st, p.splits, p.partials, p.grid, p.G); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

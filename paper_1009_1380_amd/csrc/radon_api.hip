@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 #include <new>
 #include <string>
 #include <vector>
@@ -270,36 +271,39 @@ radon_status_t sort_samples(Plan& p, std::vector<int>& offsets_host) {
 }
 
 // Work lists. Spreading: one item per chunk of the visit list of each output
-// tile of the half plane (tile column 0 holds the mx = G/2 line, columns
-// ntl/2..ntl-1 hold mx = 0..G/2-1); the visit list is the diagonal
-// neighbour's class 2, the v-neighbour's classes 2-3, the u-neighbour's
-// classes 1-2 and all of the own bin. Forward: the forward tile columns
-// ntl/2-1, .., ntl-1, 0 are taken in consecutive pairs (the last pair wraps
-// to column 0) and the rows in pairs; each 2 x 2 super-tile's samples are
-// cut into items of at most kF3Chunk.
+// strip of the half plane: A2_GX consecutive tile columns of one tile row
+// (tile column 0 holds the mx = G/2 line and is a strip of its own, columns
+// ntl/2..ntl-1 hold mx = 0..G/2-1 and are taken in runs of A2_GX). The visit
+// list of a strip is the diagonal neighbour's class 2, the v-neighbours'
+// classes 2-3, the u-neighbour's classes 1-2 and all of the own bins -- the
+// samples whose footprint reaches the strip. Forward: the forward tile
+// columns ntl/2-1, .., ntl-1, 0 are taken in consecutive pairs (the last pair
+// wraps to column 0) and the rows in pairs; each 2 x 2 super-tile's samples
+// are cut into items of at most kF3Chunk.
 radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
     const int ntl = p.ntl;
     auto run = [&](int bin, int c0, int c1) { return o4[4 * bin + c1] - o4[4 * bin + c0]; };
     std::vector<rn::TileItem> items;
     std::vector<rn::F3Item> fitems;
     std::vector<rn::SplitTile> splits;
+    std::vector<std::pair<int, int>> strips;   // (first column, columns)
+    for (int cx = std::max(ntl / 2, 1); cx < ntl; cx += rn::A2_GX) strips.push_back({cx, std::min(rn::A2_GX, ntl - cx)});
+    strips.push_back({0, 1});
     int slots = 0;
     for (int cy = 0; cy < ntl; ++cy) {
-        for (int cx = 0; cx < ntl; ++cx) {
-            const bool half = (cx == 0) || (cx >= ntl / 2);
-            if (!half) continue;
-            const int own = cy * ntl + cx;
+        for (const auto& st : strips) {
+            const int cx = st.first, gx = st.second;
             const int xl = (cx + ntl - 1) % ntl, yu = (cy + ntl - 1) % ntl;
-            const int total = run(yu * ntl + xl, 2, 3) + run(yu * ntl + cx, 2, 4) + run(cy * ntl + xl, 1, 3) +
-                              run(own, 0, 4);
+            int total = run(yu * ntl + xl, 2, 3) + run(cy * ntl + xl, 1, 3);
+            for (int j = 0; j < gx; ++j) total += run(yu * ntl + cx + j, 2, 4) + run(cy * ntl + cx + j, 0, 4);
             const int chunk = p.a2_chunk;
             if (total <= chunk) {
-                items.push_back({cx, cy, 0, total, -1, 0, 0, 0});
+                items.push_back({cx, cy, 0, total, -1, gx, 0, 0});
             } else {
                 const int nch = (total + chunk - 1) / chunk;
-                splits.push_back({cx, cy, slots, nch});
+                splits.push_back({cx, cy, slots, nch, gx});
                 for (int k = 0; k < nch; ++k)
-                    items.push_back({cx, cy, k * chunk, std::min(chunk, total - k * chunk), slots + k, 0, 0, 0});
+                    items.push_back({cx, cy, k * chunk, std::min(chunk, total - k * chunk), slots + k, gx, 0, 0});
                 slots += nch;
             }
         }
@@ -346,7 +350,7 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
     if (!fitems.empty() && (s = upload(p.fitems, fitems))) return s;
     if ((s = dev_alloc(p, &p.splits, splits.size()))) return s;
     if (!splits.empty() && (s = upload(p.splits, splits))) return s;
-    if ((s = dev_alloc(p, &p.partials, (size_t)std::max(slots, 1) * p.T * p.T))) return s;
+    if ((s = dev_alloc(p, &p.partials, (size_t)std::max(slots, 1) * rn::A2_GX * p.T * p.T))) return s;
     return RADON_OK;
 }
 
@@ -377,7 +381,6 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
     p.n_bins = p.ntl * p.ntl;
     p.n_samples = (int64_t)n_views * n_det + n_views;
     p.beta = M_PI * sqrt((W / sigma) * (W / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
-    p.kbS = (float)kKbS;
 
     // host tables in float64, rounded once
     std::vector<double2> cs(n_views);

@@ -45,7 +45,7 @@ template <int W, int T>
 static hipError_t launch_f3_wt(const Plan& p, hipStream_t st) {
     if (p.n_fitems == 0) return hipSuccess;
     hipLaunchKernelGGL((k_f3_tiles<W, T, 512>), dim3(p.f3_grid), dim3(512), 0, st, p.fitems, p.n_fitems, p.offs4,
-                       p.recs, p.grid, p.kbc, p.kbS, p.Xr, p.G);
+                       p.recs, p.grid, p.kbc, p.Xr, p.G);
     return hipGetLastError();
 }
 

@@ -46,7 +46,6 @@ struct Plan {
     int n_fitems = 0;                   // forward interpolation work
     int f3_grid = 0;                    // workgroups of the persistent forward interpolation
     int a2_chunk = 0, f3_chunk = 0;     // most visits / samples per work item
-    float kbS = 0;                      // cubic pieces per unit of t
 
     // device tables
     double2* cs = nullptr;       // per view (cos, sin), float64

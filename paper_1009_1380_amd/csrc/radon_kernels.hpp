@@ -38,47 +38,39 @@ namespace rn {
 
 // ---------------------------------------------------------------- helpers
 
-// Kaiser-Bessel weight phi(t) for t >= 0 from a table of cubic pieces, S
-// pieces per unit of t (c.x + c.y f + c.z f^2 + c.w f^3 on piece floor(t S),
-// f = frac(t S)); strict support: 0 for t >= W/2. S is a power of two, so
-// t * S is exact and the piece index stays below (W/2) S.
-// Branch-free: the piece index is clamped into the table and the result
-// selected to 0 outside the support, so all of a footprint's table reads can
-// be issued together.
-__device__ __forceinline__ float kb_weight(float t, const float4* __restrict__ tab, float S, float half_w) {
-    const float x = fminf(t, half_w) * S;
-    const int i = min((int)x, (int)(half_w * S) - 1);
-    const float f = x - (float)i;
-    const float4 c = tab[i];
-    const float w = fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
-    return t < half_w ? w : 0.0f;
-}
+// Cubic pieces of the Kaiser-Bessel table per unit of t (the host builds the
+// table with the same count).
+constexpr int KB_S = 32;
 
-// Footprint point k (0..W-1) of a sample with fraction f lies at distance
-// |f + W/2 - 1 - k|; only the two outer points (k = 0, W-1) can reach the
-// support edge W/2, where phi jumps from 1/I0(beta) (9e-4 for W = 4) to 0.
-// Whether they are inside is decided once per sample in float64 (the record's
-// edge flags, see SampleRec); the float32 distance is clamped to the largest
-// float below W/2 so that an inside point never rounds onto the edge.
-__device__ __forceinline__ float kb_edge(float half_w) { return __int_as_float(__float_as_int(half_w) - 1); }
+// Kaiser-Bessel weights phi(t), 0 <= t <= W/2, from a table of cubic pieces,
+// KB_S pieces per unit of t (c.x + c.y f + c.z f^2 + c.w f^3 on piece
+// floor(t KB_S) at f = frac(t KB_S)). A footprint along one axis has W points;
+// for a sample with fraction f in [0, 1], point k lies at distance
+// f + (W/2 - 1 - k) for k < W/2 and (k - W/2 + 1) - f otherwise. With
+// f KB_S = i + r (i integer, r in [0, 1]; f may have rounded up to 1), the
+// near points read piece (W/2 - 1 - k) KB_S + i at fraction r and the far
+// points piece (k - W/2 + 1) KB_S - i - 1 at fraction 1 - r (the end of the
+// previous piece when r = 0), so one split serves all W table reads, which
+// differ only by constant offsets, and every index stays in the table.
+// Only the two outer points (k = 0, W-1) can reach the support edge W/2,
+// where phi jumps from 1/I0(beta) (9e-4 for W = 4) to 0; whether they are
+// inside is decided once per sample in float64 (the record's edge flags, see
+// SampleRec), and the callers zero the points outside.
 template <int W>
-__device__ __forceinline__ float kb_dist(float f, int k, float edge) {
-    return fminf(fabsf(f + (float)(W / 2 - 1 - k)), edge);
+__device__ __forceinline__ void kb_weights(float f, const float4* __restrict__ tab, float (&w)[W]) {
+    const float x = f * (float)KB_S;
+    const int i = min((int)x, KB_S - 1);
+    const float r = x - (float)i, rb = 1.0f - r;
+    const float4* near = tab + i;
+    const float4* far = tab + (KB_S - 1 - i);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const bool nr = k < W / 2;
+        const float4 c = nr ? near[(W / 2 - 1 - k) * KB_S] : far[(k - W / 2) * KB_S];
+        const float t = nr ? r : rb;
+        w[k] = fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
+    }
 }
-
-// The same weight with an early exit outside the support (fewer registers
-// when the caller keeps many weights live).
-__device__ __forceinline__ float kb_weight_br(float t, const float4* __restrict__ tab, float S, float half_w) {
-    if (!(t < half_w)) return 0.0f;
-    const float x = t * S;
-    const int i = (int)x;
-    const float f = x - (float)i;
-    const float4 c = tab[i];
-    return fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
-}
-#ifndef RN_A2_KB
-#define RN_A2_KB kb_weight_br
-#endif
 
 struct SampleGeom {
     double u, v;     // grid coordinates
@@ -114,9 +106,6 @@ __device__ __forceinline__ int mod_pos(int a, int m) {
 // a mod G for a in [-G, 2G) (one compare and add instead of an integer division).
 __device__ __forceinline__ int wrap_g(int a, int G) { return a < 0 ? a + G : (a >= G ? a - G : a); }
 
-// Cubic pieces of the Kaiser-Bessel table per unit of t (the host builds the
-// table with the same count).
-constexpr int KB_S = 32;
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2). Renumber block b of nb so that each XCD gets a contiguous run of
@@ -332,7 +321,8 @@ struct TileItem {
     int start;       // first position (forward: absolute in perm; spreading: visit index)
     int count;       // number of samples / visits
     int slot;        // spreading only: -1 writes the grid, else partial slot
-    int pad0, pad1, pad2;
+    int gx;          // spreading only: tile columns of the strip
+    int pad1, pad2;
 };
 
 // Per-sample record in sorted order, built once per plan so that the
@@ -392,11 +382,15 @@ struct F3Item {
 // precomputed from the plan's per-sample records.
 constexpr int F3_CHUNK = 2048;   // samples per work item
 
+// Waves per SIMD the interpolation kernel is compiled for when W <= 6.
+#ifndef RN_F3_WPE
+#define RN_F3_WPE 6
+#endif
 template <int W, int T, int NT>
-__global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ items, int n_items,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_F3_WPE : 1))) void k_f3_tiles(const F3Item* __restrict__ items, int n_items,
                                                 const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
                                                 const float2* __restrict__ grid, const float4* __restrict__ kbc,
-                                                float kbS, float2* __restrict__ Xr, int G) {
+                                                float2* __restrict__ Xr, int G) {
     constexpr int P = 2 * T + W - 1;
     constexpr int PP = P * P;
     constexpr int PE = (PP + NT - 1) / NT;            // staged points per thread
@@ -405,8 +399,6 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
     __shared__ float4 kbt[NKB];
     const int tid = threadIdx.x;
     const int ntl = G / T;
-    const float hw = 0.5f * (float)W;
-    const float edge = kb_edge(hw);
 
     for (int e = tid; e < NKB; e += NT) kbt[e] = kbc[e];
 
@@ -446,17 +438,17 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
             if (!((unsigned)r.info & REC_F3)) continue;
             const int ox = wrap_g((r.org & REC_ORG_MASK) - x0, G);   // in [0, 2T)
             const int oy = wrap_g(((r.org >> 16) & REC_ORG_MASK) - y0, G);
-            float wy[W];
-#pragma unroll
-            for (int gm = 0; gm < W; ++gm) wy[gm] = kb_weight(kb_dist<W>(r.fv, gm, edge), kbt, kbS, hw);
+            float wy[W], wx[W];
+            kb_weights<W>(r.fv, kbt, wy);
             if (r.org & REC_V_NEAR_OUT) wy[0] = 0.f;
             if (r.org & REC_V_FAR_OUT) wy[W - 1] = 0.f;
+            kb_weights<W>(r.fu, kbt, wx);
+            if (r.org & REC_U_NEAR_OUT) wx[0] = 0.f;
+            if (r.org & REC_U_FAR_OUT) wx[W - 1] = 0.f;
             const float2* src = tile + ox * P + oy;
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
             for (int al = 0; al < W; ++al) {
-                float wx = kb_weight(kb_dist<W>(r.fu, al, edge), kbt, kbS, hw);
-                if ((al == 0 && (r.org & REC_U_NEAR_OUT)) || (al == W - 1 && (r.org & REC_U_FAR_OUT))) wx = 0.f;
                 float2 racc = make_float2(0.f, 0.f);
 #pragma unroll
                 for (int gm = 0; gm < W; ++gm) {
@@ -464,8 +456,8 @@ __global__ __launch_bounds__(NT) void k_f3_tiles(const F3Item* __restrict__ item
                     racc.x = fmaf(wy[gm], val.x, racc.x);
                     racc.y = fmaf(wy[gm], val.y, racc.y);
                 }
-                acc.x = fmaf(wx, racc.x, acc.x);
-                acc.y = fmaf(wx, racc.y, acc.y);
+                acc.x = fmaf(wx[al], racc.x, acc.x);
+                acc.y = fmaf(wx[al], racc.y, acc.y);
             }
             const bool cj = (r.info & (REC_CONJ | REC_MIRROR)) != 0;
             Xr[r.info & REC_IDX_MASK] = cj ? cconj(acc) : acc;
@@ -548,62 +540,88 @@ __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, 
 
 // ---------------------------------------------------------------- A2
 // Deterministic binned spreading. One workgroup per work item: a slice of
-// at most A2_CHUNK visits of one output tile's visit list, which is the
-// concatenation of the diagonal neighbour bin's class 2, the v-neighbour's
-// classes 2-3, the u-neighbour's classes 1-2 and the whole own bin -- exactly
-// the samples whose footprint reaches the tile. Each thread takes up to
-// A2_VPT visits and adds their W x W footprints into a halo'd LDS tile.
+// at most A2_CHUNK visits of one output strip's visit list (a strip is gx <=
+// A2_GX consecutive tile columns of one tile row), which is the concatenation
+// of the diagonal neighbour bin's class 2, the v-neighbours' classes 2-3, the
+// u-neighbour's classes 1-2 and the whole own bins -- exactly the samples
+// whose footprint reaches the strip. Each thread takes up to A2_VPT visits
+// and adds their W x W footprints into a halo'd LDS strip; strips of several
+// tiles make fewer, longer work items and visit fewer samples twice.
 //
-// The tile is accumulated in fixed point with 64-bit integer atomic adds, the
+// The strip is accumulated in fixed point with 64-bit integer atomic adds, the
 // real and imaginary parts packed into one word: a contribution (c_re, c_im)
 // of two int32 adds c_re + 2^32 c_im (mod 2^64). Integer addition is exact,
 // commutative and associative, so the word ends as S_re + 2^32 S_im (mod
 // 2^64) whatever the order in which lanes and waves arrive, and S_re, S_im are
 // recovered exactly when both lie in [-2^31, 2^31): the result is bitwise
 // reproducible without floating-point atomics, and one atomic carries both
-// parts. c = round(wx * Y * wy * 2^s), with the item's scale s chosen from
-// its largest |Y * wy| so that count * max|c| < 2^31 bounds every final sum;
-// each contribution is then rounded to 2^-22 (count 512) of the item's
-// largest one, about the resolution of float32.
+// parts. c = round(wx * (Y * wy * 2^s)), with the item's scale s chosen from
+// its largest |Y * wy| so that every |c| <= 2^21 and, with at most 512 visits
+// per item, every final sum stays below 2^30; each contribution is rounded to
+// 2^-22 of the item's largest one, about the resolution of float32.
 #ifndef RN_A2_NT
 #define RN_A2_NT 256
 #endif
 #ifndef RN_A2_CHUNK
 #define RN_A2_CHUNK 512
 #endif
+#ifndef RN_A2_GX
+#define RN_A2_GX 2
+#endif
 constexpr int A2_NT = RN_A2_NT;
 constexpr int A2_CHUNK = RN_A2_CHUNK;
 constexpr int A2_VPT = (A2_CHUNK + A2_NT - 1) / A2_NT;
+constexpr int A2_GX = RN_A2_GX;   // tile columns per strip (at most)
 
+// Waves per SIMD the spreading kernel is compiled for when W <= 6 (at most
+// 80 VGPRs; W = 8 keeps its natural allocation).
+#ifndef RN_A2_WPE
+#define RN_A2_WPE 6
+#endif
 template <int W, int T>
-__global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict__ items,
-                                                    const int* __restrict__ offs4,
-                                                    const SampleRec* __restrict__ recs,
-                                                    const float2* __restrict__ Yh,
-                                                    const float4* __restrict__ kbc, float kbS,
-                                                    float2* __restrict__ grid, float2* __restrict__ partials,
-                                                    int G) {
-    constexpr int P = T + 2 * (W - 1);   // accumulator side: local [-(W-1), T+W-1)
+__global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_A2_WPE : 1))) void k_a2_spread(
+    const TileItem* __restrict__ items, const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
+    const float2* __restrict__ Yh, const float4* __restrict__ kbc, float2* __restrict__ grid,
+    float2* __restrict__ partials, int G) {
+    constexpr int PX = A2_GX * T + 2 * (W - 1);   // accumulator: local [-(W-1), A2_GX T + W-1) along u
+    constexpr int PY = T + 2 * (W - 1);           // and [-(W-1), T + W-1) along v
     constexpr int NKB = (W / 2) * KB_S;
-    __shared__ unsigned long long acc[P * P];
+    constexpr int NR = A2_GX + 3;                 // visit ranges
+    __shared__ unsigned long long acc[PX * PY];
     __shared__ float4 kbt[NKB];
     __shared__ float wmax[A2_NT / 64];
     const int tid = threadIdx.x;
     const TileItem it = items[blockIdx.x];
+    const int gx = it.gx;
     const int ntl = G / T;
-    const float hw = 0.5f * (float)W;
-    const float edge = kb_edge(hw);
 
-    for (int e = tid; e < P * P; e += A2_NT) acc[e] = 0ull;
+    for (int e = tid; e < PX * PY; e += A2_NT) acc[e] = 0ull;
     for (int e = tid; e < NKB; e += A2_NT) kbt[e] = kbc[e];
     lds_sync();
 
+    // visit ranges: diagonal class 2, v-neighbours classes 2-3, u-neighbour
+    // classes 1-2, own bins (consecutive bins, one range)
     const int xl = (it.cx + ntl - 1) % ntl, yu = (it.cy + ntl - 1) % ntl;
-    const int b_ul = yu * ntl + xl, b_u = yu * ntl + it.cx, b_l = it.cy * ntl + xl, b_o = it.cy * ntl + it.cx;
-    const int s0 = offs4[4 * b_ul + 2], n0 = offs4[4 * b_ul + 3] - s0;
-    const int s1 = offs4[4 * b_u + 2], n1 = offs4[4 * b_u + 4] - s1;
-    const int s2 = offs4[4 * b_l + 1], n2 = offs4[4 * b_l + 3] - s2;
-    const int s3 = offs4[4 * b_o];
+    int rs[NR], rl[NR];
+    {
+        const int b = yu * ntl + xl;
+        rs[0] = offs4[4 * b + 2];
+        rl[0] = offs4[4 * b + 3] - rs[0];
+    }
+#pragma unroll
+    for (int j = 0; j < A2_GX; ++j) {
+        const int b = yu * ntl + it.cx + j;
+        rs[1 + j] = j < gx ? offs4[4 * b + 2] : 0;
+        rl[1 + j] = j < gx ? offs4[4 * b + 4] - rs[1 + j] : 0;
+    }
+    {
+        const int b = it.cy * ntl + xl;
+        rs[A2_GX + 1] = offs4[4 * b + 1];
+        rl[A2_GX + 1] = offs4[4 * b + 3] - rs[A2_GX + 1];
+        const int bo = it.cy * ntl + it.cx;
+        rs[A2_GX + 2] = offs4[4 * bo];
+        rl[A2_GX + 2] = offs4[4 * (bo + gx)] - rs[A2_GX + 2];
+    }
     const int x0 = it.cx * T, y0 = it.cy * T;
 
     int base[A2_VPT];
@@ -615,11 +633,14 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
         const int t = tid + k * A2_NT;
         base[k] = -1;
         if (t < it.count) {
-            int u = it.start + t, pos;
-            if (u < n0) pos = s0 + u;
-            else if ((u -= n0) < n1) pos = s1 + u;
-            else if ((u -= n1) < n2) pos = s2 + u;
-            else pos = s3 + (u - n2);
+            int u = it.start + t, pos = -1;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                if (pos < 0) {
+                    if (u < rl[q]) pos = rs[q] + u;
+                    else u -= rl[q];
+                }
+            }
             const SampleRec r = load_rec(recs, pos);
             float2 Y = Yh[r.info & REC_IDX_MASK];
             if (r.info & REC_CONJ) Y = cconj(Y);
@@ -629,16 +650,17 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
             if (ox < -G / 2) ox += G;
             if (oy >= G / 2) oy -= G;
             if (oy < -G / 2) oy += G;
-            base[k] = (ox + W - 1) * P + (oy + W - 1);
-#pragma unroll
-            for (int al = 0; al < W; ++al) wx[k][al] = RN_A2_KB(kb_dist<W>(r.fu, al, edge), kbt, kbS, hw);
+            base[k] = (ox + W - 1) * PY + (oy + W - 1);
+            kb_weights<W>(r.fu, kbt, wx[k]);
             if (r.org & REC_U_NEAR_OUT) wx[k][0] = 0.f;
             if (r.org & REC_U_FAR_OUT) wx[k][W - 1] = 0.f;
+            float wy[W];
+            kb_weights<W>(r.fv, kbt, wy);
+            if (r.org & REC_V_NEAR_OUT) wy[0] = 0.f;
+            if (r.org & REC_V_FAR_OUT) wy[W - 1] = 0.f;
 #pragma unroll
             for (int gm = 0; gm < W; ++gm) {
-                float wy = RN_A2_KB(kb_dist<W>(r.fv, gm, edge), kbt, kbS, hw);
-                if ((gm == 0 && (r.org & REC_V_NEAR_OUT)) || (gm == W - 1 && (r.org & REC_V_FAR_OUT))) wy = 0.f;
-                ywy[k][gm] = make_float2(Y.x * wy, Y.y * wy);
+                ywy[k][gm] = make_float2(Y.x * wy[gm], Y.y * wy[gm]);
                 mx_abs = fmaxf(mx_abs, fmaxf(fabsf(ywy[k][gm].x), fabsf(ywy[k][gm].y)));
             }
         }
@@ -651,12 +673,15 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
     float m = wmax[0];
 #pragma unroll
     for (int w = 1; w < A2_NT / 64; ++w) m = fmaxf(m, wmax[w]);
-    // scale 2^s: m * 2^s < 2^(30 - lc), so count * max|c| < 2^30 + count/2 < 2^31
+    // scale 2^s: m 2^s < 2^21, so every |c| <= 2^21 (|wx| <= 1) and a sum of
+    // count <= 512 of them stays below 2^31
     int e = 0;
     (void)frexpf(m, &e);                       // m < 2^e
-    int lc = 0;
-    while ((1 << lc) < it.count) ++lc;         // count <= 2^lc
-    const int s = 30 - lc - e;
+    const int s = 21 - e;
+    // fma(w, y, 1.5 2^23) rounds w y (|w y| < 2^22) to an integer c once and
+    // leaves 0x4B400000 + c in the bits; both words' offsets go in one subtraction
+    const float magic = 12582912.0f;
+    const unsigned long long bias = 0x4B4000004B400000ull;
 #pragma unroll
     for (int k = 0; k < A2_VPT; ++k) {
         if (base[k] < 0) continue;
@@ -665,20 +690,20 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
             const float yr = ldexpf(ywy[k][gm].x, s), yi = ldexpf(ywy[k][gm].y, s);
 #pragma unroll
             for (int al = 0; al < W; ++al) {
-                const long long cr = __float2int_rn(wx[k][al] * yr);
-                const long long ci = __float2int_rn(wx[k][al] * yi);
-                atomicAdd(&acc[base[k] + al * P + gm],
-                          (unsigned long long)cr + ((unsigned long long)ci << 32));
+                const float tr = fmaf(wx[k][al], yr, magic), ti = fmaf(wx[k][al], yi, magic);
+                const unsigned long long word =
+                    ((unsigned long long)__float_as_uint(ti) << 32) | __float_as_uint(tr);
+                atomicAdd(&acc[base[k] + al * PY + gm], word - bias);   // c_re + 2^32 c_im (mod 2^64)
             }
         }
     }
     lds_sync();
     // write out: local (lx, ly) -> mx = (x0 + lx - G/2) mod G, my = (y0 + ly - G/2) mod G
-    const int xvalid = (it.cx == 0) ? 1 : T;   // tile column 0 holds only mx = G/2
+    const int xvalid = (it.cx == 0) ? 1 : gx * T;   // tile column 0 holds only mx = G/2
     const int my0 = mod_pos(y0 - G / 2, G);
     for (int e2 = tid; e2 < xvalid * T; e2 += A2_NT) {
         const int lx = e2 / T, ly = e2 - lx * T;
-        const unsigned long long w = acc[(lx + W - 1) * P + (ly + W - 1)];
+        const unsigned long long w = acc[(lx + W - 1) * PY + (ly + W - 1)];
         const int sre = (int)(unsigned int)(w & 0xffffffffull);
         const int sim = (int)((long long)(w - (unsigned long long)(long long)sre) >> 32);
         const float2 val = make_float2((float)ldexp((double)sre, -s), (float)ldexp((double)sim, -s));
@@ -686,27 +711,29 @@ __global__ __launch_bounds__(A2_NT) void k_a2_spread(const TileItem* __restrict_
             const int mx = wrap_g(x0 + lx - G / 2, G);
             grid[(size_t)mx * G + my0 + ly] = val;
         } else {
-            partials[(size_t)it.slot * T * T + e2] = val;
+            partials[(size_t)it.slot * (A2_GX * T * T) + e2] = val;
         }
     }
 }
 
-// Sum the partial tiles of split output tiles in slot order.
+// Sum the partial strips of split output strips in slot order.
 struct SplitTile {
     int cx, cy;
     int first_slot, nslots;
+    int gx;          // tile columns of the strip
 };
 
 template <int T>
 __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__ splits,
                                                   const float2* __restrict__ partials,
                                                   float2* __restrict__ grid, int G) {
+    constexpr int SLOT = A2_GX * T * T;   // points per partial slot
     const SplitTile sp = splits[blockIdx.x];
-    const int xvalid = (sp.cx == 0) ? 1 : T;
+    const int xvalid = (sp.cx == 0) ? 1 : sp.gx * T;   // tile column 0 holds only mx = G/2
     const int x0 = sp.cx * T, y0 = sp.cy * T;
     const int my0 = mod_pos(y0 - G / 2, G);
-    const float2* src = partials + (size_t)sp.first_slot * T * T;
-    // blockIdx.y picks 256 of the tile's points, one per thread
+    const float2* src = partials + (size_t)sp.first_slot * SLOT;
+    // blockIdx.y picks 256 of the strip's points, one per thread
     for (int e = blockIdx.y * 256 + threadIdx.x; e < xvalid * T && e < (blockIdx.y + 1) * 256; e += 256) {
         // slots are added in order; the loads of eight slots are issued together
         float2 s = make_float2(0.f, 0.f);
@@ -714,12 +741,12 @@ __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__
         for (; k + 8 <= sp.nslots; k += 8) {
             float2 v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(k + j) * T * T + e];
+            for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(k + j) * SLOT + e];
 #pragma unroll
             for (int j = 0; j < 8; ++j) s = (k + j == 0) ? v[j] : cadd(s, v[j]);
         }
         for (; k < sp.nslots; ++k) {
-            const float2 v = src[(size_t)k * T * T + e];
+            const float2 v = src[(size_t)k * SLOT + e];
             s = (k == 0) ? v : cadd(s, v);
         }
         const int lx = e / T, ly = e - lx * T;
