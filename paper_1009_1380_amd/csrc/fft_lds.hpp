@@ -121,8 +121,12 @@ template <> struct Dft<8> {
     }
 };
 
-// ---- compile-time radix plan: 5s, then 3s, then the power of two as 8s
-// (a leftover 2^1 or 2^2 becomes 4x4 or 4 when there are enough factors).
+// ---- compile-time radix plan: the power of two as 8s (a leftover 2^1 or
+// 2^2 becomes 4x4 or 4 when there are enough factors), then 3s, then 5s.
+// Powers of two first keep the sub-length L of every pass a power of two
+// until the odd radices, so the pass's index split (bf mod L, bf / L) is a
+// mask and a shift, and its strided LDS positions are constant offsets from
+// one padded base (see lds_pad_step).
 
 struct RadixPlan {
     int np;
@@ -131,8 +135,6 @@ struct RadixPlan {
 
 constexpr RadixPlan make_plan(int len) {
     RadixPlan p{0, {}};
-    while (len % 5 == 0) { p.r[p.np++] = 5; len /= 5; }
-    while (len % 3 == 0) { p.r[p.np++] = 3; len /= 3; }
     int k = 0;
     while (len % 2 == 0) { ++k; len /= 2; }
     int e8 = k / 3, rem = k % 3;
@@ -142,6 +144,8 @@ constexpr RadixPlan make_plan(int len) {
         if (rem == 1) p.r[p.np++] = 2;
         if (rem == 2) p.r[p.np++] = 4;
     }
+    while (len % 3 == 0) { p.r[p.np++] = 3; len /= 3; }
+    while (len % 5 == 0) { p.r[p.np++] = 5; len /= 5; }
     if (len != 1) p.np = -1;  // unsupported factor
     return p;
 }
@@ -153,6 +157,22 @@ constexpr bool length_ok(int len) { return len >= 2 && make_plan(len).np > 0; }
 // lines are LDS_LS(LEN) elements apart.
 constexpr int lds_ls(int len) { return len + (len >> 5) + 1; }
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+// Position of element e + m*STRIDE, m = 0..R-1, given p = lds_pad(e), as p
+// plus a constant (an immediate offset of the LDS instruction) where the
+// layout allows:
+//  - STRIDE a multiple of 32: the pad grows by STRIDE/32 per step;
+//  - STRIDE dividing 32 and e = c*GROUP + j with j < STRIDE, where GROUP =
+//    STRIDE*R is a multiple of 32 (then e mod 32 = j, and the step m crosses
+//    (m*STRIDE)/32 block boundaries whatever j is) or a divisor of 32 (then
+//    all R positions share e's block); GROUP = 0 stands for e < STRIDE.
+// Otherwise the position is computed per element.
+template <int STRIDE, int GROUP>
+__device__ __forceinline__ int lds_pad_step(int p, int e, int m) {
+    if constexpr (STRIDE % 32 == 0) return p + m * (STRIDE + STRIDE / 32);
+    else if constexpr (32 % STRIDE == 0 && (GROUP % 32 == 0 || 32 % GROUP == 0))
+        return p + m * STRIDE + ((m * STRIDE) >> 5);
+    else return lds_pad(e + m * STRIDE);
+}
 
 // Twiddles w^m, m = 1..R-1, from w = w^1 by a shallow product tree (at most
 // three roundings deep), so each butterfly loads a single table entry.
@@ -185,8 +205,9 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             const int line = b / NB;
             const int bf = b - line * NB;
             const float2* src = buf + line * LS;
+            const int pb = lds_pad(bf);
 #pragma unroll
-            for (int m = 0; m < R; ++m) v[it][m] = src[lds_pad(bf + m * NB)];
+            for (int m = 0; m < R; ++m) v[it][m] = src[lds_pad_step<NB, 0>(pb, bf, m)];
         }
     }
     lds_sync();
@@ -208,8 +229,9 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             Dft<R>::run(v[it]);
             float2* dst = buf + line * LS;
             const int o = k * (L * R) + j;
+            const int po = lds_pad(o);
 #pragma unroll
-            for (int m = 0; m < R; ++m) dst[lds_pad(o + m * L)] = v[it][m];
+            for (int m = 0; m < R; ++m) dst[lds_pad_step<L, L * R>(po, o, m)] = v[it][m];
         }
     }
     lds_sync();
@@ -271,8 +293,9 @@ __device__ __forceinline__ void fft_first_from_regs(float2 (&v)[IT][R], float2* 
             const int bf = b - line * IO::NB0;
             Dft<IO::R0>::run(v[it]);
             float2* dst = buf + line * IO::LS;
+            const int po = lds_pad(bf * IO::R0);
 #pragma unroll
-            for (int m = 0; m < IO::R0; ++m) dst[lds_pad(bf * IO::R0 + m)] = v[it][m];
+            for (int m = 0; m < IO::R0; ++m) dst[lds_pad_step<1, IO::R0>(po, bf * IO::R0, m)] = v[it][m];
         }
     }
 }
@@ -303,8 +326,9 @@ __device__ __forceinline__ void fft_last_to_regs(const float2* buf, const float2
             const int line = b / IO::NBL;
             const int bf = b - line * IO::NBL;
             const float2* src = buf + line * IO::LS;
+            const int pb = lds_pad(bf);
 #pragma unroll
-            for (int m = 0; m < R; ++m) out[it][m] = src[lds_pad(bf + m * IO::NBL)];
+            for (int m = 0; m < R; ++m) out[it][m] = src[lds_pad_step<IO::NBL, 0>(pb, bf, m)];
             float2 w[R];
             twiddle_powers<R>(tw[bf], w);
 #pragma unroll
