@@ -405,6 +405,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const F3Item it = items[i];
         const int x0 = it.cx * T, y0 = it.cy * T;
+        const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
+        const int b0 = it.cy * ntl + it.cx, b1 = it.cy * ntl + cx1, b2 = cy1 * ntl + it.cx, b3 = cy1 * ntl + cx1;
+        const int s0 = offs4[4 * b0], n0 = offs4[4 * b0 + 4] - s0;
+        const int s1 = offs4[4 * b1], n1 = (it.nbx > 1) ? offs4[4 * b1 + 4] - s1 : 0;
+        const int s2 = offs4[4 * b2], n2 = offs4[4 * b2 + 4] - s2;
+        const int s3 = offs4[4 * b3];
+        auto position = [&](int k) {
+            int u = it.start + k;
+            if (u < n0) return s0 + u;
+            if ((u -= n0) < n1) return s1 + u;
+            if ((u -= n1) < n2) return s2 + u;
+            return s3 + (u - n2);
+        };
+        // the first record is requested before the staging, and each next one
+        // before the current one is interpolated, so record latency overlaps work
+        SampleRec nxt{};
+        if (tid < it.count) nxt = load_rec(recs, position(tid));
         lds_sync();   // the previous item's samples are done with the tile
         // stage the region; points with mx < 0 hold the conjugate of their mirror
 #pragma unroll
@@ -422,19 +439,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_
             }
         }
         lds_sync();
-        const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
-        const int b0 = it.cy * ntl + it.cx, b1 = it.cy * ntl + cx1, b2 = cy1 * ntl + it.cx, b3 = cy1 * ntl + cx1;
-        const int s0 = offs4[4 * b0], n0 = offs4[4 * b0 + 4] - s0;
-        const int s1 = offs4[4 * b1], n1 = (it.nbx > 1) ? offs4[4 * b1 + 4] - s1 : 0;
-        const int s2 = offs4[4 * b2], n2 = offs4[4 * b2 + 4] - s2;
-        const int s3 = offs4[4 * b3];
         for (int k = tid; k < it.count; k += NT) {
-            int u = it.start + k, pos;
-            if (u < n0) pos = s0 + u;
-            else if ((u -= n0) < n1) pos = s1 + u;
-            else if ((u -= n1) < n2) pos = s2 + u;
-            else pos = s3 + (u - n2);
-            const SampleRec r = load_rec(recs, pos);
+            const SampleRec r = nxt;
+            if (k + NT < it.count) nxt = load_rec(recs, position(k + NT));
             if (!((unsigned)r.info & REC_F3)) continue;
             const int ox = wrap_g((r.org & REC_ORG_MASK) - x0, G);   // in [0, 2T)
             const int oy = wrap_g(((r.org >> 16) & REC_ORG_MASK) - y0, G);
