@@ -198,6 +198,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
     constexpr int IT = (TOT + NT - 1) / NT;
     constexpr bool FULL = (TOT % NT) == 0;
     float2 v[IT][R];
+    float2 w1[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int b = tid + it * NT;
@@ -208,6 +209,9 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             const int pb = lds_pad(bf);
 #pragma unroll
             for (int m = 0; m < R; ++m) v[it][m] = src[lds_pad_step<NB, 0>(pb, bf, m)];
+            // the twiddle is requested before the barrier, so its latency
+            // overlaps the wait for the other waves
+            if constexpr (L > 1) w1[it] = tw[(bf % L) * (LEN / (L * R))];
         }
     }
     lds_sync();
@@ -220,9 +224,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             const int j = bf % L;
             const int k = bf / L;
             if constexpr (L > 1) {
-                constexpr int STEP = LEN / (L * R);
                 float2 w[R];
-                twiddle_powers<R>(tw[j * STEP], w);
+                twiddle_powers<R>(w1[it], w);
 #pragma unroll
                 for (int m = 1; m < R; ++m) v[it][m] = cmul(v[it][m], w[m]);
             }
