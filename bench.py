@@ -397,6 +397,11 @@ def main():
         "plan_s": round(t_plan, 3),
         "pair_alg_bytes": pair_bytes,
         "pair_alg_GBps": round(pair_bytes / (ms_step * 1e-3) / 1e9, 1),
+        # the same pair priced with the full-complex-grid byte model (every
+        # pass over the whole G x G grid: 200 n^2 + 8 M bytes), as a fraction
+        # of the 8 TB/s HBM peak
+        "pair_full_grid_model_bytes": 200 * N_IMG * N_IMG + 8 * N_VIEWS * N_DET,
+        "pair_full_grid_model_frac": round((200 * N_IMG * N_IMG + 8 * N_VIEWS * N_DET) / (ms_step * 1e-3) / 8.0e12, 4),
         "stages": stages,
         "roofline": roofline,
     }
