@@ -17,9 +17,9 @@
 //                of the tile, of the samples sorted into it -> Xr[a][|q|]
 //            F4  per pair of rays: complex-to-real inverse FFT -> sinogram
 //   adjoint  A1  per pair of rays: real-to-complex FFT -> Yh[a][q], q <= N/2
-//            A2  per output tile: deterministic spreading of the samples
-//                that reach the tile into an LDS accumulator, no atomics on
-//                floating-point data
+//            A2  per output strip of tiles: deterministic spreading of the
+//                samples that reach the strip into an LDS accumulator, no
+//                atomics on floating-point data
 //            A3  each grid line -> inverse column FFT, keep n rows -> T1
 //            A4  pairs of image rows: complex-to-real inverse row FFT,
 //                keep n columns, deapodize -> image
