@@ -58,7 +58,7 @@ def kernel_bytes(n: int, n_views: int, n_det: int):
 
 
 # the files that define the path's kernels and their launch shapes
-KERNEL_SOURCES = ("fft_lds.hpp", "radon_kernels.hpp", "radon_sort.hpp", "radon_fwd.hip", "radon_adj.hip")
+KERNEL_SOURCES = ("fft_lds.hpp", "radon_kernels.hpp", "radon_sort.hpp", "radon_fwd.hip", "radon_adj.hip", "radon_api.hip")
 
 
 def source_hash() -> str:

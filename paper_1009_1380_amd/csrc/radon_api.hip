@@ -290,13 +290,26 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
     for (int cx = std::max(ntl / 2, 1); cx < ntl; cx += rn::A2_GX) strips.push_back({cx, std::min(rn::A2_GX, ntl - cx)});
     strips.push_back({0, 1});
     int slots = 0;
+    const int chunk = p.a2_chunk;
+    auto strip_total = [&](int cx, int cy, int gx) {
+        const int xl = (cx + ntl - 1) % ntl, yu = (cy + ntl - 1) % ntl;
+        int total = run(yu * ntl + xl, 2, 3) + run(cy * ntl + xl, 1, 3);
+        for (int j = 0; j < gx; ++j) total += run(yu * ntl + cx + j, 2, 4) + run(cy * ntl + cx + j, 0, 4);
+        return total;
+    };
     for (int cy = 0; cy < ntl; ++cy) {
-        for (const auto& st : strips) {
+        for (const auto& st0 : strips) {
+            // a strip too long for one item is cut back to single tiles: their
+            // partial sums are half as many, which shortens the reduction
+            std::vector<std::pair<int, int>> parts;
+            if (st0.second > 1 && strip_total(st0.first, cy, st0.second) > chunk) {
+                for (int j = 0; j < st0.second; ++j) parts.push_back({st0.first + j, 1});
+            } else {
+                parts.push_back(st0);
+            }
+            for (const auto& st : parts) {
             const int cx = st.first, gx = st.second;
-            const int xl = (cx + ntl - 1) % ntl, yu = (cy + ntl - 1) % ntl;
-            int total = run(yu * ntl + xl, 2, 3) + run(cy * ntl + xl, 1, 3);
-            for (int j = 0; j < gx; ++j) total += run(yu * ntl + cx + j, 2, 4) + run(cy * ntl + cx + j, 0, 4);
-            const int chunk = p.a2_chunk;
+            const int total = strip_total(cx, cy, gx);
             if (total <= chunk) {
                 items.push_back({cx, cy, 0, total, -1, gx, 0, 0});
             } else {
@@ -305,6 +318,7 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
                 for (int k = 0; k < nch; ++k)
                     items.push_back({cx, cy, k * chunk, std::min(chunk, total - k * chunk), slots + k, gx, 0, 0});
                 slots += nch;
+            }
             }
         }
     }
