@@ -730,6 +730,9 @@ struct SplitTile {
     int gx;          // tile columns of the strip
 };
 
+#ifndef RN_A2R_FLIGHT
+#define RN_A2R_FLIGHT 16
+#endif
 template <int T>
 __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__ splits,
                                                   const float2* __restrict__ partials,
@@ -742,19 +745,17 @@ __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__
     const float2* src = partials + (size_t)sp.first_slot * SLOT;
     // blockIdx.y picks 256 of the strip's points, one per thread
     for (int e = blockIdx.y * 256 + threadIdx.x; e < xvalid * T && e < (blockIdx.y + 1) * 256; e += 256) {
-        // slots are added in order; the loads of eight slots are issued together
+        // slots are added in order; the loads of RN_A2R_FLIGHT slots (the last batch
+        // predicated) are issued together
         float2 s = make_float2(0.f, 0.f);
-        int k = 0;
-        for (; k + 8 <= sp.nslots; k += 8) {
-            float2 v[8];
+        for (int k = 0; k < sp.nslots; k += RN_A2R_FLIGHT) {
+            float2 v[RN_A2R_FLIGHT];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(k + j) * SLOT + e];
+            for (int j = 0; j < RN_A2R_FLIGHT; ++j)
+                v[j] = (k + j < sp.nslots) ? src[(size_t)(k + j) * SLOT + e] : make_float2(0.f, 0.f);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s = (k + j == 0) ? v[j] : cadd(s, v[j]);
-        }
-        for (; k < sp.nslots; ++k) {
-            const float2 v = src[(size_t)k * SLOT + e];
-            s = (k == 0) ? v : cadd(s, v);
+            for (int j = 0; j < RN_A2R_FLIGHT; ++j)
+                if (k + j < sp.nslots) s = (k + j == 0) ? v[j] : cadd(s, v[j]);
         }
         const int lx = e / T, ly = e - lx * T;
         const int mx = wrap_g(x0 + lx - G / 2, G);
