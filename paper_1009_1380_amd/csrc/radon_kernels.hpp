@@ -130,20 +130,19 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 constexpr int row_waves(int len) { return len <= 2560 ? 8 : 4; }
 
 template <int NL, int NT>
-__device__ __forceinline__ void f1_store(float2* __restrict__ T1, const float2* lds, int m, int k, int kc, int i0) {
+__device__ __forceinline__ void f1_store(float2* __restrict__ T1, const float2* lds, int m, int k, int kc, int i0,
+                                         int p) {
+    // line p gives rows i0 + 2p and i0 + 2p + 1 (16 bytes); the lanes of a pair
+    // take p = 0 and 1 of one frequency, so one store instruction fills 32 whole
+    // 32-byte pieces
     constexpr int LS = lds_ls(NL);
-    float2 o[4];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        const float2 zk = lds[p * LS + lds_pad(k)];
-        const float2 zc = cconj(lds[p * LS + lds_pad(kc)]);
-        const float2 sm = cadd(zk, zc), df = csub(zk, zc);
-        o[2 * p] = make_float2(0.5f * sm.x, 0.5f * sm.y);
-        o[2 * p + 1] = make_float2(0.5f * df.y, -0.5f * df.x);   // (zk - zc) / 2i
-    }
-    float2* dst = T1 + (size_t)m * NL + i0;
-    if (i0 + 1 < NL) *reinterpret_cast<float4*>(dst) = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
-    if (i0 + 3 < NL) *reinterpret_cast<float4*>(dst + 2) = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+    const float2 zk = lds[p * LS + lds_pad(k)];
+    const float2 zc = cconj(lds[p * LS + lds_pad(kc)]);
+    const float2 sm = cadd(zk, zc), df = csub(zk, zc);
+    const float2 o0 = make_float2(0.5f * sm.x, 0.5f * sm.y);
+    const float2 o1 = make_float2(0.5f * df.y, -0.5f * df.x);   // (zk - zc) / 2i
+    float2* dst = T1 + (size_t)m * NL + i0 + 2 * p;
+    if (i0 + 2 * p + 1 < NL) *reinterpret_cast<float4*>(dst) = make_float4(o0.x, o0.y, o1.x, o1.y);
 }
 
 template <int NL, int NT>
@@ -178,7 +177,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
     }
     lds_sync();
     fft_lds<NL, 2, NT>(lds, tw, tid);
-    for (int k = tid; k <= NL / 2; k += NT) f1_store<NL, NT>(T1, lds, 2 * k, k, (NL - k) % NL, i0);
+    for (int e = tid; e < 2 * (NL / 2 + 1); e += NT) {
+        const int k = e >> 1;
+        f1_store<NL, NT>(T1, lds, 2 * k, k, (NL - k) % NL, i0, e & 1);
+    }
     lds_sync();
 #pragma unroll
     for (int c = 0; c < PJ; ++c) {
@@ -192,7 +194,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
     }
     lds_sync();
     fft_lds<NL, 2, NT>(lds, tw, tid);
-    for (int k = tid; k < NL / 2; k += NT) f1_store<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0);
+    for (int e = tid; e < 2 * (NL / 2); e += NT) {
+        const int k = e >> 1;
+        f1_store<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e & 1);
+    }
 }
 
 // ---------------------------------------------------------------- F2
@@ -854,27 +859,21 @@ __global__ __launch_bounds__(NT) void k_a3_cols(const float2* __restrict__ grid,
 // wait in registers), then the O lines; each T1[mx][i0..i0+3] (32 contiguous
 // bytes) is read once, by the pass of its parity.
 template <int NL, int NT>
-__device__ __forceinline__ void a4_load(const float2* __restrict__ T1, float2* lds, int m, int pk, int pc, int i0) {
+__device__ __forceinline__ void a4_load(const float2* __restrict__ T1, float2* lds, int m, int pk, int pc, int i0,
+                                        int p) {
+    // line p takes rows i0 + 2p and i0 + 2p + 1 (16 bytes); the lanes of a pair
+    // take p = 0 and 1 of one frequency, so one load instruction reads 32 whole
+    // 32-byte pieces
     constexpr int LS = lds_ls(NL);
-    const float2* src = T1 + (size_t)m * NL + i0;
-    const float4 v01 = *reinterpret_cast<const float4*>(src);
-    float4 v23 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i0 + 3 < NL) v23 = *reinterpret_cast<const float4*>(src + 2);
-    float2 X[4] = {make_float2(v01.x, v01.y), make_float2(v01.z, v01.w), make_float2(v23.x, v23.y),
-                   make_float2(v23.z, v23.w)};
-    if (m == 0 || m == NL) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) X[q].y = 0.f;
-    }
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        const float2 X1 = X[2 * p], X2 = X[2 * p + 1];
-        const float2 z = make_float2(X1.x - X2.y, X1.y + X2.x);             // X1 + i X2
-        lds[p * LS + lds_pad(pk)] = cconj(z);                               // conjugated for the inverse
-        if (m >= 1 && m <= NL - 1) {
-            const float2 zm = make_float2(X1.x + X2.y, -X1.y + X2.x);       // conj X1 + i conj X2 at 2n - m
-            lds[p * LS + lds_pad(pc)] = cconj(zm);
-        }
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i0 + 2 * p + 1 < NL) v = *reinterpret_cast<const float4*>(T1 + (size_t)m * NL + i0 + 2 * p);
+    float2 X1 = make_float2(v.x, v.y), X2 = make_float2(v.z, v.w);
+    if (m == 0 || m == NL) { X1.y = 0.f; X2.y = 0.f; }
+    const float2 z = make_float2(X1.x - X2.y, X1.y + X2.x);             // X1 + i X2
+    lds[p * LS + lds_pad(pk)] = cconj(z);                               // conjugated for the inverse
+    if (m >= 1 && m <= NL - 1) {
+        const float2 zm = make_float2(X1.x + X2.y, -X1.y + X2.x);       // conj X1 + i conj X2 at 2n - m
+        lds[p * LS + lds_pad(pc)] = cconj(zm);
     }
 }
 
@@ -889,7 +888,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
     const int tid = threadIdx.x;
     const int i0 = 4 * xcd_block(blockIdx.x, gridDim.x);
     // even mx = 2k: position k, mirror 2n - 2k at n - k
-    for (int k = tid; k <= NL / 2; k += NT) a4_load<NL, NT>(T1, lds, 2 * k, k, NL - k, i0);
+    for (int e = tid; e < 2 * (NL / 2 + 1); e += NT) {
+        const int k = e >> 1;
+        a4_load<NL, NT>(T1, lds, 2 * k, k, NL - k, i0, e & 1);
+    }
     lds_sync();
     fft_lds<NL, 2, NT>(lds, tw, tid);
     float2 e[PJ][2];
@@ -904,7 +906,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
     }
     lds_sync();
     // odd mx = 2k+1: position k, mirror 2n - 2k - 1 at n - 1 - k
-    for (int k = tid; k < NL / 2; k += NT) a4_load<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0);
+    for (int e = tid; e < 2 * (NL / 2); e += NT) {
+        const int k = e >> 1;
+        a4_load<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e & 1);
+    }
     lds_sync();
     fft_lds<NL, 2, NT>(lds, tw, tid);
 #pragma unroll
