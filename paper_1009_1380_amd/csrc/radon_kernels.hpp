@@ -599,7 +599,7 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
     constexpr int PY = T + 2 * (W - 1);           // and [-(W-1), T + W-1) along v
     constexpr int NKB = (W / 2) * KB_S;
     constexpr int NR = A2_GX + 3;                 // visit ranges
-    __shared__ unsigned long long acc[PX * PY];
+    __shared__ __align__(16) unsigned long long acc[PX * PY];
     __shared__ float4 kbt[NKB];
     __shared__ float wmax[A2_NT / 64];
     const int tid = threadIdx.x;
@@ -607,7 +607,9 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
     const int gx = it.gx;
     const int ntl = G / T;
 
-    for (int e = tid; e < PX * PY; e += A2_NT) acc[e] = 0ull;
+    // T is even, so PX * PY is: clear the accumulator 16 bytes at a time
+    static_assert(T % 2 == 0 && (PX * PY) % 2 == 0, "accumulator cleared in pairs of words");
+    for (int e = tid; e < PX * PY / 2; e += A2_NT) reinterpret_cast<ulonglong2*>(acc)[e] = make_ulonglong2(0ull, 0ull);
     for (int e = tid; e < NKB; e += A2_NT) kbt[e] = kbc[e];
     lds_sync();
 
@@ -713,17 +715,25 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
     // write out: local (lx, ly) -> mx = (x0 + lx - G/2) mod G, my = (y0 + ly - G/2) mod G
     const int xvalid = (it.cx == 0) ? 1 : gx * T;   // tile column 0 holds only mx = G/2
     const int my0 = mod_pos(y0 - G / 2, G);
-    for (int e2 = tid; e2 < xvalid * T; e2 += A2_NT) {
+    // two consecutive my per lane, one 16-byte store: T, y0 and G/2 (= n)
+    // are even, so my0 + ly is even and the pair never leaves the tile
+    for (int e2 = 2 * tid; e2 < xvalid * T; e2 += 2 * A2_NT) {
         const int lx = e2 / T, ly = e2 - lx * T;
-        const unsigned long long w = acc[(lx + W - 1) * PY + (ly + W - 1)];
-        const int sre = (int)(unsigned int)(w & 0xffffffffull);
-        const int sim = (int)((long long)(w - (unsigned long long)(long long)sre) >> 32);
-        const float2 val = make_float2((float)ldexp((double)sre, -s), (float)ldexp((double)sim, -s));
+        float v[4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const unsigned long long w = acc[(lx + W - 1) * PY + (ly + h + W - 1)];
+            const int sre = (int)(unsigned int)(w & 0xffffffffull);
+            const int sim = (int)((long long)(w - (unsigned long long)(long long)sre) >> 32);
+            v[2 * h] = (float)ldexp((double)sre, -s);
+            v[2 * h + 1] = (float)ldexp((double)sim, -s);
+        }
+        const float4 val = make_float4(v[0], v[1], v[2], v[3]);
         if (it.slot < 0) {
             const int mx = wrap_g(x0 + lx - G / 2, G);
-            grid[(size_t)mx * G + my0 + ly] = val;
+            *reinterpret_cast<float4*>(grid + (size_t)mx * G + my0 + ly) = val;
         } else {
-            partials[(size_t)it.slot * (A2_GX * T * T) + e2] = val;
+            *reinterpret_cast<float4*>(partials + (size_t)it.slot * (A2_GX * T * T) + e2) = val;
         }
     }
 }

@@ -248,6 +248,9 @@ def test_batched_equals_loop():
     a = plan.adjoint_batched(ys)
     for b in range(B):
         assert torch.equal(a[b], plan.adjoint(ys[b].contiguous()))
+    # an empty batch is a no-op that launches nothing
+    assert plan.forward_batched(xs[:0]).shape == (0, nv, n)
+    assert plan.adjoint_batched(ys[:0]).shape == (0, n, n)
 
 
 def test_binding_rejects_bad_tensors():
