@@ -88,31 +88,85 @@ def load_traffic(kernel: str, n_launch_bytes: int):
     return k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(n_views_sample: int):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_views_sample: int, dev=None):
     """Time the FP64 oracle (forward + adjoint) on a bounded sample: the same
-    image and detector, every (1024/n_views_sample)-th view."""
+    image and detector, every (1024/n_views_sample)-th view. With `dev`, the
+    GPU path runs on the same input and geometry and its relative L2 error
+    against the oracle's outputs is returned too (forward on the phantom;
+    adjoint on the oracle's forward output rounded to float32)."""
     import numpy as np
 
     from oracle.grid import _WORKERS, grid_adjoint, grid_forward
     from radon_inputs import config2_phantom, uniform_angles
 
-    x = config2_phantom(0, N_IMG).astype(np.float64)
+    x32 = config2_phantom(0, N_IMG)
+    x = x32.astype(np.float64)
     ang = uniform_angles(N_VIEWS)[:: N_VIEWS // n_views_sample]
     t0 = time.perf_counter()
     y = grid_forward(x, ang, N_DET, SIGMA, W)
     t1 = time.perf_counter()
-    grid_adjoint(y, ang, N_IMG, SIGMA, W)
+    y32 = y.astype(np.float32)
+    a = grid_adjoint(y32.astype(np.float64), ang, N_IMG, SIGMA, W)
     t2 = time.perf_counter()
     samples = len(ang) * N_DET
-    return {
+    out = {
         "value": samples / (t2 - t0) / 1e9,
         "unit": "Gsamples/s",
         "cores": int(_WORKERS),
         "kind": "oracle",
+        "host_cpu_count": os.cpu_count(),
+        "cpu_model": cpu_model(),
         "sample": (f"FP64 O-grid forward+adjoint of the 2560^2 disk phantom on {len(ang)} of the "
                    f"1024 views x 2560 bins ({samples} samples): fwd {t1 - t0:.2f} s, "
-                   f"adj {t2 - t1:.2f} s; scipy.fft workers and BLAS threads as listed"),
+                   f"adj {t2 - t1:.2f} s; scipy.fft with {_WORKERS} workers (the host share of one GPU "
+                   f"is 16 threads), NumPy footprint sums"),
     }
+    err = None
+    if dev is not None:
+        import torch
+
+        from paper_1009_1380_amd import Plan
+
+        plan = Plan(N_IMG, ang, N_DET, SIGMA, W)
+        yg = plan.forward(torch.from_numpy(x32).to(dev)).cpu().numpy().astype(np.float64)
+        ag = plan.adjoint(torch.from_numpy(y32).to(dev)).cpu().numpy().astype(np.float64)
+        plan.close()
+        err = {"fwd": float(np.linalg.norm(yg - y) / np.linalg.norm(y)),
+               "adj": float(np.linalg.norm(ag - a) / np.linalg.norm(a)),
+               "views": len(ang), "tolerance": 1e-5}
+    return out, err
+
+
+def copy_peak(dev, mib: int = 2048, reps: int = 10):
+    """Device-to-device copy of a buffer much larger than the 256 MB last-level
+    cache; bytes read + written per second (GB/s)."""
+    import torch
+
+    n = mib * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3 / reps
+    del src, dst
+    return 2 * n * 4 / sec / 1e9
 
 
 SOLVE_SNR_DB = 30.0     # noise level of the reduced-view data
@@ -342,6 +396,22 @@ def main():
     t_fwd = time_loop(lambda: plan.forward(x, out=sino, stream=stream), args.steps)
     t_adj = time_loop(lambda: plan.adjoint(sino, out=back, stream=stream), args.steps)
 
+    # cold last-level cache: a 1 GiB buffer is written before every pair (the
+    # 256 MB cache then holds none of the pair's arrays); only the pair is timed
+    flush = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    cold = []
+    for _ in range(args.steps):
+        flush.fill_(1.0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        cold.append(a.elapsed_time(b))
+    del flush
+    ms_cold = float(np.median(cold))
+    copy_gbs = copy_peak(dev)
+
     # per-kernel durations: same steps with each launch bracketed by events
     plan.set_profiling(True)
     for _ in range(args.steps):
@@ -368,6 +438,8 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": load_traffic(dominant, d["alg_bytes"]),
+        "copy_peak": round(copy_gbs, 1),
+        "frac_of_copy_peak": round(achieved / copy_gbs, 4),
     }
     samples = N_VIEWS * N_DET
     value = samples / (ms_step * 1e-3) / 1e9
@@ -395,13 +467,21 @@ def main():
         "t_adj_ms": round(t_adj, 4),
         "wall_s_timed": round(wall, 4),
         "plan_s": round(t_plan, 3),
+        "ms_per_step_cold_cache": round(ms_cold, 4),
+        "copy_peak_GBps": round(copy_gbs, 1),
+        # the bytes this design moves per pair (Hermitian half plane, each
+        # array once per kernel that touches it) over the pair's time
         "pair_alg_bytes": pair_bytes,
         "pair_alg_GBps": round(pair_bytes / (ms_step * 1e-3) / 1e9, 1),
-        # the same pair priced with the full-complex-grid byte model (every
-        # pass over the whole G x G grid: 200 n^2 + 8 M bytes), as a fraction
-        # of the 8 TB/s HBM peak
-        "pair_full_grid_model_bytes": 200 * N_IMG * N_IMG + 8 * N_VIEWS * N_DET,
-        "pair_full_grid_model_frac": round((200 * N_IMG * N_IMG + 8 * N_VIEWS * N_DET) / (ms_step * 1e-3) / 8.0e12, 4),
+        "pair_frac_hbm_peak": round(pair_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "pair_frac_copy_peak": round(pair_bytes / (ms_step * 1e-3) / 1e9 / copy_gbs, 4),
+        "pair_frac_hbm_peak_cold_cache": round(pair_bytes / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the byte model of the full complex G x G grid (200 n^2 + 8 M per
+        # pair), which this design does not move; kept for comparison only
+        "full_grid_model": {
+            "bytes": 200 * N_IMG * N_IMG + 8 * N_VIEWS * N_DET,
+            "frac_hbm_peak": round((200 * N_IMG * N_IMG + 8 * N_VIEWS * N_DET) / (ms_step * 1e-3) / 8.0e12, 4),
+        },
         "stages": stages,
         "roofline": roofline,
     }
@@ -425,7 +505,7 @@ def main():
         line["warmstart"] = warmstart_times()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.cpu_views)
+        line["cpu_baseline"], line["rel_l2_vs_ogrid"] = cpu_baseline(args.cpu_views, dev)
     else:
         line["cpu_baseline"] = None
     plan.close()

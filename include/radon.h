@@ -252,6 +252,8 @@ typedef struct {
     int max_iter;      /* iteration limit                                                  */
     int ring_filter;   /* 1: operator F A and data F b; 0: F = identity                    */
     int warm_start;    /* 1: x_dev holds the starting image and tau0 = ||x0||_1; 0: x0 = 0 */
+    int fallback_iters;/* warm start: iterations without a new least residual before the
+                          cold solver takes over (<= 0: 100)                              */
 } radon_solve_opts;
 
 typedef struct {
@@ -263,7 +265,19 @@ typedef struct {
     int n_forward;     /* radon_forward applications                                       */
     int n_adjoint;     /* radon_adjoint applications                                       */
     int status;        /* 0 iteration limit, 1 basis-pursuit solution, 2 root found        */
+    int fallback;      /* why a warm start was abandoned for a cold solve (RADON_FALLBACK_*) */
+    int warm_iterations; /* iterations the abandoned warm run took (0 without fallback)    */
 } radon_solve_stats;
+
+/* Reasons a warm start is abandoned; the cold-started solver then runs with the
+ * whole iteration budget, and its result is returned. */
+enum {
+    RADON_FALLBACK_NONE = 0,
+    RADON_FALLBACK_NONFINITE = 1,        /* start, its l1 norm, residual or objective not finite  */
+    RADON_FALLBACK_WORSE_THAN_ZERO = 2,  /* ||F(A x0 - b)|| >= ||F b||: x0 fits no better than 0 */
+    RADON_FALLBACK_ITER_LIMIT = 3,       /* the warm run reached max_iter                          */
+    RADON_FALLBACK_STALLED = 4           /* no new least residual within fallback_iters iterations */
+};
 
 /*
  * Basis-pursuit denoising min ||x||_1 s.t. ||F(A x - b)||_2 <= sigma (the
@@ -276,6 +290,18 @@ typedef struct {
  * fixed order, so results are bitwise reproducible. The call allocates its
  * workspace, runs on `stream` and synchronises it (it reads a few float64
  * scalars per iteration); stats may be NULL.
+ * Warm starts: the cold-started solver is the fallback. A warm run is
+ * abandoned for a cold one (stats->fallback says why) when x0 or its first
+ * residual is not finite, when x0 fits the data no better than zero, when it
+ * reaches max_iter, or when fallback_iters iterations pass without a new
+ * least residual. A warm start may lie above the root of the Pareto curve,
+ * where a point with ||r|| = sigma need not have the least l1 norm, so a warm
+ * run stops at the root only after its first Newton update of tau (which,
+ * the curve being convex and decreasing, leaves tau at or below the root).
+ * Errors: RADON_ERR_INVALID for NULL pointers, sigma < 0 or not finite,
+ * opt_tol <= 0, max_iter < 1, a non-finite sinogram, or a cold run whose
+ * objective becomes non-finite; RADON_ERR_OOM when the workspace cannot be
+ * allocated; RADON_ERR_DEVICE for launch or copy failures.
  */
 radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev, float* x_dev, const radon_solve_opts* opts,
                                 radon_solve_stats* stats, void* stream);

@@ -421,41 +421,43 @@ extern "C" radon_status_t radon_ring_filter(radon_plan_t plan, const float* y_de
     return RADON_OK;
 }
 
-extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev, float* x_dev,
-                                           const radon_solve_opts* opts, radon_solve_stats* stats, void* stream) {
-    if (!plan || !b_dev || !x_dev || !opts) return RADON_ERR_INVALID;
-    if (!(opts->sigma >= 0) || !(opts->opt_tol > 0) || opts->max_iter < 1) return RADON_ERR_INVALID;
-    const auto t0 = std::chrono::steady_clock::now();
-    const rn::Plan& p = plan->p;
-    SolveWork w;
-    const size_t n2 = (size_t)p.n * p.n, ns = (size_t)p.n_views * p.n_det;
-    if (!w.alloc(&w.x, n2) || !w.alloc(&w.xn, n2) || !w.alloc(&w.h, n2) || !w.alloc(&w.hn, n2) ||
-        !w.alloc(&w.z, ns) || !w.alloc(&w.r, ns) || !w.alloc(&w.rn, ns) || !w.alloc(&w.bt, ns) ||
-        !w.alloc(&w.m, p.n_det) || !w.alloc(&w.ring, p.n_det) || !w.alloc(&w.Q, (size_t)p.n_det * 4) ||
-        !w.alloc(&w.part, (size_t)rn::SV_SLOTS * rn::SV_BLOCKS) || !w.alloc(&w.fin, FIN_COUNT) ||
-        !w.alloc(&w.lam, 2) || !w.alloc(&w.pj, (size_t)2 * rn::PJ_BLOCKS) || !w.alloc(&w.ticket, 1))
-        return RADON_ERR_OOM;
-    // projection state: threshold 0 (no warm start yet), ticket 0
-    hipLaunchKernelGGL(rn::k_sv_zero, dim3(1), dim3(64), 0, (hipStream_t)stream, w.lam, w.ticket);
-    hipStream_t st = (hipStream_t)stream;
-    Solver S{plan, p, w, st, opts->ring_filter != 0, b_dev, n2, ns};
-    const std::vector<double> Q = cubic_basis(p.n_det);
-    S.chk(hipMemcpyAsync(w.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice, st));
+namespace {
 
+// Outcome of one SPGL1 run from the start held in w.x.
+struct RunOut {
+    int status = 0;       // 0 iteration limit, 1 basis pursuit, 2 root
+    int it = 0;           // iterations taken
+    double f = 0, tau = 0;
+    int fallback = 0;     // why a warm run was abandoned (RADON_FALLBACK_*), 0 if it was not
+};
+
+// One SPGL1 run. `warm`: w.x holds the start image (tau0 = its l1 norm), else
+// the run starts from zero. A warm run is abandoned, and reports why in
+// out.fallback, when its start is non-finite, when it fits the data no better
+// than x = 0, when its residual norm stops decreasing for `stall_iters`
+// iterations, or when it reaches the iteration limit; the caller then runs
+// cold. A warm start may lie above the Pareto root (tau0 > tau*), where a
+// point with ||r|| = sigma need not have the least l1 norm; such a run is
+// not allowed to stop at the root before its first Newton update of tau,
+// which (the Pareto curve being convex and decreasing) leaves tau at or
+// below the root, as a cold run's tau always is.
+radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, bool warm, double bnorm,
+                         RunOut& out) {
     const double sigma = opts->sigma, opt_tol = opts->opt_tol, bp_tol = opts->bp_tol, dec_tol = opts->dec_tol;
     const double bb_min = 1e-16, bb_max = 1e5;   // spectral step bounds
     const int n_mem = 3;
+    const int stall_iters = opts->fallback_iters > 0 ? opts->fallback_iters : 100;
+    hipStream_t st = S.st;
     double fin[FIN_COUNT];
-    // b~ = F b and its norm
-    S.residual(nullptr, w.bt, nullptr);
-    if (!S.read(fin)) return RADON_ERR_DEVICE;
-    const double bnorm = sqrt(fin[FIN_RES]);
+    out = RunOut{};
+    // projection state: threshold 0 (no warm start yet), ticket 0
+    hipLaunchKernelGGL(rn::k_sv_zero, dim3(1), dim3(64), 0, st, w.lam, w.ticket);
     // start point, tau = ||x0||_1, and the projection of x0 (a no-op at that radius)
-    if (opts->warm_start) S.chk(hipMemcpyAsync(w.x, x_dev, sizeof(float) * n2, hipMemcpyDeviceToDevice, st));
-    else hipLaunchKernelGGL(rn::k_sv_fill, dim3(1024), dim3(256), 0, st, w.x, n2, 0.0f);
+    if (!warm) hipLaunchKernelGGL(rn::k_sv_fill, dim3(1024), dim3(256), 0, st, w.x, S.n2, 0.0f);
     S.bb(nullptr, w.x, nullptr, w.x);
     if (!S.read(fin)) return RADON_ERR_DEVICE;
     double tau = fin[FIN_BB + 3];
+    if (warm && !std::isfinite(tau)) { out.fallback = RADON_FALLBACK_NONFINITE; return RADON_OK; }
     if (!S.project_sync(w.x, w.x, 0.0, tau, w.xn, fin)) return RADON_ERR_DEVICE;
     std::swap(w.x, w.xn);
     // r = F(b - A x), h = A^T r
@@ -466,9 +468,15 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
     if (!S.read(fin)) return RADON_ERR_DEVICE;
     double f = 0.5 * fin[FIN_RES], rbt = fin[FIN_RES + 1];
     double gnorm = fin[FIN_BB + 2];
+    if (warm) {
+        if (!std::isfinite(f) || !std::isfinite(gnorm)) { out.fallback = RADON_FALLBACK_NONFINITE; return RADON_OK; }
+        if (sqrt(2 * f) >= bnorm) { out.fallback = RADON_FALLBACK_WORSE_THAN_ZERO; return RADON_OK; }
+    }
     std::vector<double> fs(n_mem, f);
     double alpha = std::min(std::max(gnorm > 0 ? 1.0 / gnorm : 1.0, bb_min), bb_max);
-    double f_old = INFINITY;
+    double f_old = INFINITY, f_best = f;
+    int it_best = 0;
+    bool newton_taken = !warm || tau == 0.0;   // a start at zero lies below the root
     int status = 0, it = 0;
     for (it = 1; it <= opts->max_iter; ++it) {
         const double rnorm = sqrt(2 * f);
@@ -479,7 +487,11 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
         const double rerr2 = fabs(f - 0.5 * sigma * sigma) / std::max(1.0, f);
         if (rgap <= std::max(opt_tol, rerr2) || rerr1 <= opt_tol) {
             if (rnorm <= bp_tol * bnorm) { status = 1; break; }
-            if (rerr1 <= opt_tol) { status = 2; break; }
+            if (rerr1 <= opt_tol && newton_taken) { status = 2; break; }
+        }
+        if (warm) {
+            if (f < f_best) { f_best = f; it_best = it; }
+            else if (it - it_best >= stall_iters) { out.fallback = RADON_FALLBACK_STALLED; break; }
         }
         const double change = fabs(f - f_old);
         const bool stalled = (change <= dec_tol * f && rnorm > 2 * sigma) ||
@@ -487,6 +499,7 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
         if (stalled && gnorm > 0) {
             const double tau_old = tau;
             tau = std::max(0.0, tau + rnorm * aerr1 / gnorm);   // Newton step on the Pareto curve
+            newton_taken = true;
             if (tau < tau_old) {
                 // the ball shrank: restart from the projected iterate with its
                 // own residual and gradient
@@ -523,8 +536,12 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
             const double gtd = fin[FIN_PROJ];
             fn = 0.5 * fin[FIN_RES];
             rbtn = fin[FIN_RES + 1];
-            if (fn <= fmax + 1e-4 * gtd || step < 1e-10) break;
+            if (fn <= fmax + 1e-4 * gtd || step < 1e-10 || !std::isfinite(fn)) break;
             step *= 0.5;
+        }
+        if (!std::isfinite(fn)) {
+            if (warm) { out.fallback = RADON_FALLBACK_NONFINITE; break; }
+            return rn::api_fail(RADON_ERR_INVALID, "radon_solve_bpdn: the objective became non-finite");
         }
         const double sts = fin[FIN_BB], sty = fin[FIN_BB + 1];
         alpha = sty <= 0 ? bb_max : std::min(std::max(sts / sty, bb_min), bb_max);
@@ -539,19 +556,76 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
         fs.push_back(f);
     }
     if (it > opts->max_iter) it = opts->max_iter;
+    if (warm && !out.fallback && status == 0) out.fallback = RADON_FALLBACK_ITER_LIMIT;
+    out.status = status;
+    out.it = it;
+    out.f = f;
+    out.tau = tau;
+    return RADON_OK;
+}
+
+}  // namespace
+
+extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev, float* x_dev,
+                                           const radon_solve_opts* opts, radon_solve_stats* stats, void* stream) {
+    if (!plan || !b_dev || !x_dev || !opts) return RADON_ERR_INVALID;
+    if (!(opts->sigma >= 0) || !std::isfinite(opts->sigma) || !(opts->opt_tol > 0) || opts->max_iter < 1)
+        return RADON_ERR_INVALID;
+    const auto t0 = std::chrono::steady_clock::now();
+    const rn::Plan& p = plan->p;
+    SolveWork w;
+    const size_t n2 = (size_t)p.n * p.n, ns = (size_t)p.n_views * p.n_det;
+    if (!w.alloc(&w.x, n2) || !w.alloc(&w.xn, n2) || !w.alloc(&w.h, n2) || !w.alloc(&w.hn, n2) ||
+        !w.alloc(&w.z, ns) || !w.alloc(&w.r, ns) || !w.alloc(&w.rn, ns) || !w.alloc(&w.bt, ns) ||
+        !w.alloc(&w.m, p.n_det) || !w.alloc(&w.ring, p.n_det) || !w.alloc(&w.Q, (size_t)p.n_det * 4) ||
+        !w.alloc(&w.part, (size_t)rn::SV_SLOTS * rn::SV_BLOCKS) || !w.alloc(&w.fin, FIN_COUNT) ||
+        !w.alloc(&w.lam, 2) || !w.alloc(&w.pj, (size_t)2 * rn::PJ_BLOCKS) || !w.alloc(&w.ticket, 1))
+        return RADON_ERR_OOM;
+    hipStream_t st = (hipStream_t)stream;
+    Solver S{plan, p, w, st, opts->ring_filter != 0, b_dev, n2, ns};
+    const std::vector<double> Q = cubic_basis(p.n_det);
+    S.chk(hipMemcpyAsync(w.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice, st));
+
+    double fin[FIN_COUNT];
+    // b~ = F b and its norm
+    S.residual(nullptr, w.bt, nullptr);
+    if (!S.read(fin)) return RADON_ERR_DEVICE;
+    const double bnorm = sqrt(fin[FIN_RES]);
+    if (!std::isfinite(bnorm)) return rn::api_fail(RADON_ERR_INVALID, "radon_solve_bpdn: the sinogram is not finite");
+
+    RunOut run;
+    int fallback = 0, warm_it = 0;
+    radon_status_t rc;
+    if (opts->warm_start) {
+        S.chk(hipMemcpyAsync(w.x, x_dev, sizeof(float) * n2, hipMemcpyDeviceToDevice, st));
+        rc = spgl1_run(S, w, opts, true, bnorm, run);
+        if (rc != RADON_OK) return rc;
+        if (run.fallback) {
+            // the cold-started solver takes over, with the whole iteration budget
+            fallback = run.fallback;
+            warm_it = run.it;
+            rc = spgl1_run(S, w, opts, false, bnorm, run);
+            if (rc != RADON_OK) return rc;
+        }
+    } else {
+        rc = spgl1_run(S, w, opts, false, bnorm, run);
+        if (rc != RADON_OK) return rc;
+    }
     // ||x||_1 of the result, then hand it back
     S.bb(nullptr, w.x, nullptr, w.x);
     S.chk(hipMemcpyAsync(x_dev, w.x, sizeof(float) * n2, hipMemcpyDeviceToDevice, st));
     if (!S.read(fin)) return RADON_ERR_DEVICE;
     if (stats) {
-        stats->rnorm = sqrt(2 * f);
-        stats->tau = tau;
+        stats->rnorm = sqrt(2 * run.f);
+        stats->tau = run.tau;
         stats->x_l1 = fin[FIN_BB + 3];
-        stats->iterations = it;
+        stats->iterations = run.it;
         stats->n_forward = S.nf;
         stats->n_adjoint = S.na;
-        stats->status = status;
+        stats->status = run.status;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->fallback = fallback;
+        stats->warm_iterations = warm_it;
     }
-    return RADON_OK;
+    return rn::api_ok();
 }

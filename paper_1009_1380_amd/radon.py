@@ -85,13 +85,14 @@ class Tuning(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("opt_tol", ctypes.c_double), ("bp_tol", ctypes.c_double),
                 ("dec_tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("ring_filter", ctypes.c_int),
-                ("warm_start", ctypes.c_int)]
+                ("warm_start", ctypes.c_int), ("fallback_iters", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("rnorm", ctypes.c_double), ("tau", ctypes.c_double), ("x_l1", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("iterations", ctypes.c_int), ("n_forward", ctypes.c_int),
-                ("n_adjoint", ctypes.c_int), ("status", ctypes.c_int)]
+                ("n_adjoint", ctypes.c_int), ("status", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("warm_iterations", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -287,16 +288,19 @@ class Plan:
         return out
 
     def solve_bpdn(self, sino, sigma: float, x0=None, opt_tol: float = 1e-4, bp_tol: float = 1e-6,
-                   dec_tol: float = 1e-4, max_iter: int = 500, ring_filter: bool = True, stream=None):
+                   dec_tol: float = 1e-4, max_iter: int = 500, ring_filter: bool = True, stream=None,
+                   fallback_iters: int = 100):
         """min ||x||_1 s.t. ||F(A x - sino)||_2 <= sigma (SPGL1). x0: optional
-        warm-start image. Returns (x, stats dict)."""
+        warm-start image; the library falls back to a cold solve when the warm
+        run misbehaves (stats["fallback"] says why, 0 if it did not).
+        Returns (x, stats dict)."""
         torch = _torch()
         if x0 is None:
             x = torch.zeros((self.n, self.n), dtype=torch.float32, device=sino.device)
         else:
             x = x0.clone()
         opts = SolveOpts(float(sigma), float(opt_tol), float(bp_tol), float(dec_tol), int(max_iter),
-                         int(bool(ring_filter)), int(x0 is not None))
+                         int(bool(ring_filter)), int(x0 is not None), int(fallback_iters))
         stats = SolveStats()
         _check(lib().radon_solve_bpdn(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
                                       _dev_ptr(x, (self.n, self.n), "x"), ctypes.byref(opts), ctypes.byref(stats),

@@ -117,3 +117,64 @@ def test_reduced_view_solve_full_size():
     note(f"warm {sw}")
     assert sw["status"] == 2 and abs(sw["rnorm"] - sigma) <= 2e-3 * sigma
     assert abs(sw["x_l1"] - sc["x_l1"]) <= 2e-2 * sc["x_l1"]
+
+
+def _fallback_problem():
+    n, nv = 64, 48
+    _, ang, b = _problem(n, nv, seed=3)
+    plan = Plan(n, ang, n)
+    bd = to_dev(b)
+    sigma = 0.03 * float(torch.linalg.norm(plan.ring_filter(bd).double()))
+    return plan, bd, sigma
+
+
+def test_warm_start_fallback_nonfinite_and_bad_scale():
+    """The cold-started solver is the warm start's fallback: a NaN-filled
+    start and a start scaled 1e6 times (it fits the data worse than zero) are
+    both abandoned before any iteration, and the call returns exactly the
+    cold solve (same iterate, bit for bit)."""
+    note("warm-start fallback: NaN and 1e6-scaled starts")
+    plan, bd, sigma = _fallback_problem()
+    xc, sc = plan.solve_bpdn(bd, sigma, max_iter=2000)
+    assert sc["status"] == 2 and sc["fallback"] == 0
+    x_nan = torch.full((plan.n, plan.n), float("nan"), device=DEV)
+    xn, sn = plan.solve_bpdn(bd, sigma, x0=x_nan, max_iter=2000)
+    note(f"NaN start {sn}")
+    assert sn["fallback"] == 1 and sn["status"] == 2 and sn["warm_iterations"] == 0
+    assert torch.equal(xn, xc) and sn["x_l1"] == sc["x_l1"]
+    x_inf = torch.zeros((plan.n, plan.n), device=DEV)
+    x_inf[3, 5] = float("inf")
+    xi, si = plan.solve_bpdn(bd, sigma, x0=x_inf, max_iter=2000)
+    assert si["fallback"] == 1 and torch.equal(xi, xc)
+    x_big = plan.fbp(bd) * 1e6
+    xb, sb = plan.solve_bpdn(bd, sigma, x0=x_big, max_iter=2000)
+    note(f"1e6-scaled start {sb}")
+    assert sb["fallback"] == 2 and sb["status"] == 2
+    assert torch.equal(xb, xc) and sb["x_l1"] == sc["x_l1"]
+
+
+def test_warm_start_fallback_iteration_limit():
+    """A warm run that reaches the iteration limit hands over to a cold run
+    with the whole budget; the result is the cold run's."""
+    note("warm-start fallback: iteration limit")
+    plan, bd, sigma = _fallback_problem()
+    xc, sc = plan.solve_bpdn(bd, sigma, max_iter=3)
+    assert sc["status"] == 0
+    xw, sw = plan.solve_bpdn(bd, sigma, x0=plan.fbp(bd), max_iter=3)
+    assert sw["fallback"] == 3 and sw["warm_iterations"] == 3
+    assert torch.equal(xw, xc) and sw["iterations"] == sc["iterations"]
+
+
+def test_warm_start_above_root_reaches_cold_l1():
+    """A start above the Pareto root (1.2 times the cold solution, so tau0 =
+    1.2 tau*) must not stop at a feasible point with a larger l1 norm: the
+    warm run is kept (no fallback) and ends at the cold run's l1 norm to the
+    tolerance of the root finding."""
+    note("warm start above the root")
+    plan, bd, sigma = _fallback_problem()
+    xc, sc = plan.solve_bpdn(bd, sigma, opt_tol=1e-5, max_iter=5000)
+    xw, sw = plan.solve_bpdn(bd, sigma, x0=xc * 1.2, opt_tol=1e-5, max_iter=5000)
+    note(f"cold {sc}\nwarm {sw}")
+    assert sw["status"] == 2 and sw["fallback"] == 0
+    assert abs(sw["rnorm"] - sigma) <= 2e-5 * sigma
+    assert abs(sw["x_l1"] - sc["x_l1"]) <= 2e-3 * sc["x_l1"]
