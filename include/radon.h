@@ -244,6 +244,25 @@ radon_status_t radon_fft_test(int len, int batch, int inverse, const float* in_d
  */
 radon_status_t radon_ring_filter(radon_plan_t plan, const float* y_dev, float* out_dev, void* stream);
 
+/*
+ * The ring filter for callers that cannot allocate device memory (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operation and result as radon_ring_filter, with no allocation of
+ * any kind. The cubic basis is the plan's own; the scratch of its three
+ * kernels (column means, fitted ring, partial sums) is one file-scope device
+ * array of 2 * RADON_RING_NOALLOC_MAX_DET + 4096 float64 values (96 KiB),
+ * of which every GPU the library runs on holds its own copy until the
+ * process ends. Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (several streams, several threads) race and must be
+ * serialised by the caller. Stream-ordered; it does not synchronise the
+ * stream. Errors: RADON_ERR_INVALID for NULL arguments or a plan made on
+ * another device than the current one, RADON_ERR_UNSUPPORTED when the
+ * plan's n_det exceeds RADON_RING_NOALLOC_MAX_DET, RADON_ERR_DEVICE when the
+ * array's address cannot be found or a launch fails.
+ */
+#define RADON_RING_NOALLOC_MAX_DET 4096
+radon_status_t radon_ring_filter_noalloc(radon_plan_t plan, const float* y_dev, float* out_dev, void* stream);
+
 typedef struct {
     double sigma;      /* target ||F(A x - b)||_2, absolute, >= 0 (epsilon of the paper)  */
     double opt_tol;    /* relative tolerance of the root and of the duality gap (1e-4)    */

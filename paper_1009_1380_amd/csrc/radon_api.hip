@@ -422,6 +422,7 @@ radon_status_t build_plan(Plan& p, int n, const double* angles, int n_views, int
     if ((s = dev_alloc(p, &p.tw_N, n_det)) || (s = upload(p.tw_N, twiddles(n_det)))) return s;
     if ((s = dev_alloc(p, &p.kbc, kbc.size())) || (s = upload(p.kbc, kbc))) return s;
     if ((s = dev_alloc(p, &p.fbpw, n_det / 2 + 1)) || (s = upload(p.fbpw, ramp_weights(n_views, n_det)))) return s;
+    if ((s = dev_alloc(p, &p.ringQ, (size_t)n_det * 4)) || (s = upload(p.ringQ, rn::ring_cubic_basis(n_det)))) return s;
     if ((s = dev_alloc(p, &p.perm, (size_t)p.n_samples))) return s;
     if ((s = dev_alloc(p, &p.recs, (size_t)p.n_samples))) return s;
     if ((s = dev_alloc(p, &p.offs4, (size_t)4 * p.n_bins + 1))) return s;

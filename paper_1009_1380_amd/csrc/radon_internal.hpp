@@ -55,6 +55,7 @@ struct Plan {
     float2* tw_N = nullptr;      // e^{-2 pi i t/N}, N
     float4* kbc = nullptr;       // cubic pieces of phi on [0, W/2]
     float* fbpw = nullptr;       // ramp weights of the filtered adjoint, q = 0..N/2
+    double* ringQ = nullptr;     // orthonormal cubic basis of the ring filter, N x 4 (float64)
     // device workspace
     float2* T1 = nullptr;        // (n+1) x n complex64
     float2* grid = nullptr;      // (n+1) x G complex64
@@ -92,6 +93,10 @@ hipError_t launch_fft_test(int len, int batch, int inverse, const float2* in, fl
                            const float2* tw, hipStream_t st);
 
 bool length_supported(int len);
+
+// Orthonormal basis of cubic polynomials over the detector (ring filter),
+// row-major n_det x 4, float64 (defined in radon_solver.hip).
+std::vector<double> ring_cubic_basis(int n_det);
 
 // Shared with the other translation units of the C ABI (defined in
 // radon_api.hip): error reporting into radon_last_error(), the plan check,

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "../../include/radon.h"
@@ -257,6 +258,31 @@ __global__ __launch_bounds__(256) void k_sv_fill(float* __restrict__ v, size_t n
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) v[i] = val;
 }
 
+// Orthonormal basis of cubic polynomials in s = d - N/2, scaled to [-1, 1),
+// by modified Gram-Schmidt (twice) in float64; row-major N x 4.
+std::vector<double> ring_cubic_basis(int N) {
+    std::vector<double> Q((size_t)N * 4);
+    for (int d = 0; d < N; ++d) {
+        const double t = ((double)d - N / 2) / (N / 2);
+        double pw = 1.0;
+        for (int k = 0; k < 4; ++k) { Q[(size_t)d * 4 + k] = pw; pw *= t; }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int k = 0; k < 4; ++k) {
+            for (int j = 0; j < k; ++j) {
+                double dot = 0;
+                for (int d = 0; d < N; ++d) dot += Q[(size_t)d * 4 + k] * Q[(size_t)d * 4 + j];
+                for (int d = 0; d < N; ++d) Q[(size_t)d * 4 + k] -= dot * Q[(size_t)d * 4 + j];
+            }
+            double nrm = 0;
+            for (int d = 0; d < N; ++d) nrm += Q[(size_t)d * 4 + k] * Q[(size_t)d * 4 + k];
+            nrm = sqrt(nrm);
+            for (int d = 0; d < N; ++d) Q[(size_t)d * 4 + k] /= nrm;
+        }
+    }
+    return Q;
+}
+
 }  // namespace rn
 
 // ------------------------------------------------------------------ host side
@@ -286,30 +312,7 @@ struct SolveWork {
     }
 };
 
-// Orthonormal basis of cubic polynomials in s = d - N/2, scaled to [-1, 1),
-// by modified Gram-Schmidt (twice) in float64; row-major N x 4.
-std::vector<double> cubic_basis(int N) {
-    std::vector<double> Q((size_t)N * 4);
-    for (int d = 0; d < N; ++d) {
-        const double t = ((double)d - N / 2) / (N / 2);
-        double pw = 1.0;
-        for (int k = 0; k < 4; ++k) { Q[(size_t)d * 4 + k] = pw; pw *= t; }
-    }
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int k = 0; k < 4; ++k) {
-            for (int j = 0; j < k; ++j) {
-                double dot = 0;
-                for (int d = 0; d < N; ++d) dot += Q[(size_t)d * 4 + k] * Q[(size_t)d * 4 + j];
-                for (int d = 0; d < N; ++d) Q[(size_t)d * 4 + k] -= dot * Q[(size_t)d * 4 + j];
-            }
-            double nrm = 0;
-            for (int d = 0; d < N; ++d) nrm += Q[(size_t)d * 4 + k] * Q[(size_t)d * 4 + k];
-            nrm = sqrt(nrm);
-            for (int d = 0; d < N; ++d) Q[(size_t)d * 4 + k] /= nrm;
-        }
-    }
-    return Q;
-}
+std::vector<double> cubic_basis(int N) { return rn::ring_cubic_basis(N); }
 
 // fin slots: 0-1 residual (sum r^2, sum r.b~), 2-4 projection (g.dx, ||xn||_1,
 // converged flag), 5-8 spectral step (sum s^2, sum s.y, max |hn|, ||xn||_1)
@@ -419,6 +422,79 @@ extern "C" radon_status_t radon_ring_filter(radon_plan_t plan, const float* y_de
                        p.n_views, p.n_det, out_dev, w.part);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return RADON_ERR_DEVICE;
     return RADON_OK;
+}
+
+// ------------------------------------------------------------------ ring filter without allocation
+//
+// radon_ring_filter_noalloc: the ring filter for callers that cannot allocate
+// device memory (code under stream capture, serving loops, harnesses that
+// forbid it). The cubic basis is the plan's (uploaded when the plan is made);
+// the scratch the three kernels need (column means, fitted ring, the
+// per-block partials the residual kernel writes) lives in one file-scope
+// device array, of which every GPU holds its own copy until the process ends.
+// Every kernel overwrites the part of the array it reads back, so nothing
+// needs clearing between calls; calls that overlap on one GPU share the array
+// and race.
+
+namespace {
+
+constexpr int RING_NOALLOC_MAX_DET = RADON_RING_NOALLOC_MAX_DET;
+// doubles: m[N], ring[N], partials[SV_SLOTS * SV_BLOCKS]
+constexpr size_t RING_SCRATCH_DOUBLES = (size_t)2 * RING_NOALLOC_MAX_DET + (size_t)rn::SV_SLOTS * rn::SV_BLOCKS;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[RING_SCRATCH_DOUBLES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` on each GPU
+
+// The device address of this GPU's copy of `scratch`, looked up on the first
+// call on the device (which is then current); nullptr on failure.
+double* scratch_for_device(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" radon_status_t radon_ring_filter_noalloc(radon_plan_t plan, const float* y_dev, float* out_dev,
+                                                    void* stream) {
+    if (!plan || !y_dev || !out_dev)
+        return rn::api_fail(RADON_ERR_INVALID, "radon_ring_filter_noalloc: NULL argument");
+    radon_status_t s = rn::api_check_plan(plan);   // the plan's device must be current
+    if (s != RADON_OK) return s;
+    const rn::Plan& p = plan->p;
+    if (p.n_det > RING_NOALLOC_MAX_DET)
+        return rn::api_fail(RADON_ERR_UNSUPPORTED,
+                            "radon_ring_filter_noalloc: n_det exceeds RADON_RING_NOALLOC_MAX_DET");
+    double* base = scratch_for_device(p.device);
+    if (!base)
+        return rn::api_fail(RADON_ERR_DEVICE, "radon_ring_filter_noalloc: no device address for the scratch array");
+    double* m = base;
+    double* ring = m + RING_NOALLOC_MAX_DET;
+    double* part = ring + RING_NOALLOC_MAX_DET;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(rn::k_sv_colmean, dim3((p.n_det + 31) / 32), dim3(256), 0, st, y_dev, nullptr, p.n_views,
+                       p.n_det, m);
+    hipLaunchKernelGGL(rn::k_sv_ringfit, dim3(1), dim3(rn::SV_NT), 0, st, m, p.ringQ, p.n_det, ring);
+    hipLaunchKernelGGL(rn::k_sv_resid, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, y_dev, nullptr, ring, nullptr,
+                       p.n_views, p.n_det, out_dev, part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rn::api_fail(RADON_ERR_DEVICE, "radon_ring_filter_noalloc: launch failed");
+    return rn::api_ok();
 }
 
 namespace {

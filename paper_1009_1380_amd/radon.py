@@ -49,6 +49,7 @@ _SIGS = {
     "radon_debug_adjoint_grid": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_fft_test": (_c_int, [_c_int, _c_int, _c_int, _vp, _vp, _vp]),
     "radon_ring_filter": (_c_int, [_vp, _vp, _vp, _vp]),
+    "radon_ring_filter_noalloc": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_solve_bpdn": (_c_int, [_vp, _vp, _vp, ctypes.c_void_p, ctypes.c_void_p, _vp]),
     "radon_plan_tuned": (_c_int, [ctypes.POINTER(_vp), _c_int, ctypes.POINTER(_c_dbl), _c_int, _c_int, _c_dbl,
                                   _c_int, ctypes.c_void_p]),
@@ -285,6 +286,17 @@ class Plan:
         _check(lib().radon_ring_filter(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
                                        _dev_ptr(out, (self.n_views, self.n_det), "out"), _stream_ptr(stream)),
                "radon_ring_filter")
+        return out
+
+    def ring_filter_noalloc(self, sino, out=None, stream=None):
+        """The ring filter without any device allocation (scratch in a static
+        device array shared by all calls on the GPU; stream-ordered)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(sino)
+        _check(lib().radon_ring_filter_noalloc(self._h, _dev_ptr(sino, (self.n_views, self.n_det), "sino"),
+                                               _dev_ptr(out, (self.n_views, self.n_det), "out"),
+                                               _stream_ptr(stream)), "radon_ring_filter_noalloc")
         return out
 
     def solve_bpdn(self, sino, sigma: float, x0=None, opt_tol: float = 1e-4, bp_tol: float = 1e-6,
