@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -114,13 +115,31 @@ std::vector<float> ramp_weights(int n_views, int N) {
 
 bool is_supported_length(int len) { return rn::length_supported(len); }
 
+// Failure-injection hook for the tests: with RADON_TEST_FAIL_ALLOC=k in the
+// environment, the k-th device allocation made while building a plan
+// (counting from 1) fails as if the device were out of memory.
+int test_fail_alloc_at() {
+    const char* e = getenv("RADON_TEST_FAIL_ALLOC");
+    return e ? atoi(e) : 0;
+}
+
+// hipMalloc, counted against the plan's failure-injection hook.
+hipError_t plan_malloc(Plan& p, void** ptr, size_t bytes) {
+    ++p.n_allocs;
+    if (p.fail_alloc_at > 0 && p.n_allocs == p.fail_alloc_at) {
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(ptr, bytes);
+}
+
 template <class T>
 radon_status_t dev_alloc(Plan& p, T** out, size_t count) {
     *out = nullptr;
     if (count == 0) count = 1;
     void* ptr = nullptr;
     const size_t bytes = count * sizeof(T);
-    if (hipMalloc(&ptr, bytes) != hipSuccess) {
+    if (plan_malloc(p, &ptr, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(RADON_ERR_OOM, "hipMalloc of %zu bytes failed", bytes);
     }
@@ -235,9 +254,17 @@ radon_status_t sort_samples(Plan& p, std::vector<int>& offsets_host) {
         for (int* x : {k0, k1, v0, v1, hist})
             if (x) (void)hipFree(x);
     };
-    if (hipMalloc(&k0, sizeof(int) * total) != hipSuccess || hipMalloc(&k1, sizeof(int) * total) != hipSuccess ||
-        hipMalloc(&v0, sizeof(int) * total) != hipSuccess || hipMalloc(&v1, sizeof(int) * total) != hipSuccess ||
-        hipMalloc(&hist, sizeof(int) * rn::SORT_RADIX * nblocks) != hipSuccess) {
+    void* ptr[5] = {};
+    const size_t bytes[5] = {sizeof(int) * total, sizeof(int) * total, sizeof(int) * total, sizeof(int) * total,
+                             sizeof(int) * rn::SORT_RADIX * nblocks};
+    bool got = true;
+    for (int i = 0; i < 5 && got; ++i) got = plan_malloc(p, &ptr[i], bytes[i]) == hipSuccess;
+    k0 = (int*)ptr[0];
+    k1 = (int*)ptr[1];
+    v0 = (int*)ptr[2];
+    v1 = (int*)ptr[3];
+    hist = (int*)ptr[4];
+    if (!got) {
         (void)hipGetLastError();
         cleanup();
         return fail(RADON_ERR_OOM, "sort scratch allocation failed");
@@ -519,6 +546,7 @@ radon_status_t radon_plan_tuned(radon_plan_t* out, int n, const double* angles, 
 
     radon_plan_s* plan = new (std::nothrow) radon_plan_s();
     if (!plan) return fail(RADON_ERR_OOM, "host allocation failed");
+    plan->p.fail_alloc_at = test_fail_alloc_at();
     if (hipGetDevice(&plan->p.device) != hipSuccess) {
         (void)hipGetLastError();
         delete plan;

@@ -70,6 +70,8 @@ struct Plan {
     float2* partials = nullptr;
     size_t bytes = 0;
     std::vector<void*> allocs;
+    int n_allocs = 0;        // device allocations made while building the plan
+    int fail_alloc_at = 0;   // failure-injection hook (RADON_TEST_FAIL_ALLOC), 0: off
 
     bool profiling = false;
     double stage_ms[ST_COUNT] = {};

@@ -582,6 +582,9 @@ __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, 
 #endif
 constexpr int A2_NT = RN_A2_NT;
 constexpr int A2_CHUNK = RN_A2_CHUNK;
+// the fixed-point scale below keeps every sum of at most 512 contributions
+// inside int32
+static_assert(A2_CHUNK <= 512, "A2 items hold at most 512 visits");
 constexpr int A2_VPT = (A2_CHUNK + A2_NT - 1) / A2_NT;
 constexpr int A2_GX = RN_A2_GX;   // tile columns per strip (at most)
 
@@ -675,7 +678,9 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
 #pragma unroll
             for (int gm = 0; gm < W; ++gm) {
                 ywy[k][gm] = make_float2(Y.x * wy[gm], Y.y * wy[gm]);
-                mx_abs = fmaxf(mx_abs, fmaxf(fabsf(ywy[k][gm].x), fabsf(ywy[k][gm].y)));
+                // a NaN counts as infinite, so a non-finite value reaches the maximum
+                const float ax = fabsf(ywy[k][gm].x), ay = fabsf(ywy[k][gm].y);
+                mx_abs = fmaxf(mx_abs, fmaxf(ax == ax ? ax : INFINITY, ay == ay ? ay : INFINITY));
             }
         }
     }
@@ -687,10 +692,13 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
     float m = wmax[0];
 #pragma unroll
     for (int w = 1; w < A2_NT / 64; ++w) m = fmaxf(m, wmax[w]);
+    // a non-finite contribution makes the whole item NaN (written below), so
+    // divergence is not hidden by the fixed-point sums
+    const bool finite = m <= 3.402823466e38f;
     // scale 2^s: m 2^s < 2^21, so every |c| <= 2^21 (|wx| <= 1) and a sum of
     // count <= 512 of them stays below 2^31
     int e = 0;
-    (void)frexpf(m, &e);                       // m < 2^e
+    (void)frexpf(finite ? m : 0.f, &e);        // m < 2^e
     const int s = 21 - e;
     // fma(w, y, 1.5 2^23) rounds w y (|w y| < 2^22) to an integer c once and
     // leaves 0x4B400000 + c in the bits; both words' offsets go in one subtraction
@@ -698,7 +706,7 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
     const unsigned long long bias = 0x4B4000004B400000ull;
 #pragma unroll
     for (int k = 0; k < A2_VPT; ++k) {
-        if (base[k] < 0) continue;
+        if (base[k] < 0 || !finite) continue;
 #pragma unroll
         for (int gm = 0; gm < W; ++gm) {
             const float yr = ldexpf(ywy[k][gm].x, s), yi = ldexpf(ywy[k][gm].y, s);
@@ -725,8 +733,8 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
             const unsigned long long w = acc[(lx + W - 1) * PY + (ly + h + W - 1)];
             const int sre = (int)(unsigned int)(w & 0xffffffffull);
             const int sim = (int)((long long)(w - (unsigned long long)(long long)sre) >> 32);
-            v[2 * h] = (float)ldexp((double)sre, -s);
-            v[2 * h + 1] = (float)ldexp((double)sim, -s);
+            v[2 * h] = finite ? (float)ldexp((double)sre, -s) : __int_as_float(0x7fc00000);
+            v[2 * h + 1] = finite ? (float)ldexp((double)sim, -s) : __int_as_float(0x7fc00000);
         }
         const float4 val = make_float4(v[0], v[1], v[2], v[3]);
         if (it.slot < 0) {

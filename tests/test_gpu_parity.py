@@ -399,3 +399,75 @@ def test_largest_supported_size_vs_oracle():
     ag = plan.adjoint(to_dev(y)).cpu().numpy()
     assert rel(yg, grid_forward(x.astype(np.float64), ang, n)) < TOL_GRID
     assert rel(ag, grid_adjoint(y.astype(np.float64), ang, n)) < TOL_GRID
+
+
+@pytest.mark.parametrize("kind", ["beyond_pi", "negative", "duplicated", "unsorted_wide"])
+def test_unusual_angle_sets_vs_oracle(kind):
+    """The header accepts any float64 angles in any order: angles in
+    [pi, 2 pi), negative angles, repeated angles and an unsorted set spanning
+    several turns all match O-grid (and O-exact) through the ABI."""
+    note(f"angles {kind}")
+    n, n_det, nv = 32, 40, 17
+    rng = np.random.default_rng(7)
+    if kind == "beyond_pi":
+        ang = np.pi + rng.uniform(0, np.pi, nv)
+        ang[0] = np.pi
+        ang[1] = 1.5 * np.pi
+    elif kind == "negative":
+        ang = -rng.uniform(0, np.pi, nv)
+        ang[0] = -np.pi / 2
+    elif kind == "duplicated":
+        base = rng.uniform(0, np.pi, 6)
+        ang = np.concatenate([base, base, base[:5]])
+        ang[0] = ang[6] = 0.0
+    else:
+        ang = rng.uniform(-3 * np.pi, 3 * np.pi, nv)
+    x = random_image(91, n)
+    y = random_sinogram(92, nv, n_det)
+    plan = Plan(n, ang, n_det)
+    yg = plan.forward(to_dev(x)).cpu().numpy()
+    ag = plan.adjoint(to_dev(y)).cpu().numpy()
+    x64, y64 = x.astype(np.float64), y.astype(np.float64)
+    assert rel(yg, grid_forward(x64, ang, n_det)) < TOL_GRID
+    assert rel(ag, grid_adjoint(y64, ang, n)) < TOL_GRID
+    assert rel(yg, radon_exact(x64, ang, n_det)) < TOL_EXACT
+    assert rel(ag, radon_exact_adjoint(y64, ang, n)) < TOL_EXACT
+    if kind == "duplicated":
+        # repeated views give identical rows
+        assert np.array_equal(yg[0], yg[6]) and np.array_equal(yg[1], yg[7])
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_adjoint_propagates_nonfinite_input(bad):
+    """A non-finite sinogram value reaches the adjoint image as non-finite
+    values: the spreading's fixed-point sums do not turn it into finite
+    numbers (which would hide a diverging solve)."""
+    note(f"adjoint with a {bad} in the sinogram")
+    n, nv = 128, 180
+    plan = Plan(n, uniform_angles(nv), n)
+    y = random_sinogram(93, nv, n)
+    y[37, 61] = bad
+    a = plan.adjoint(to_dev(y)).cpu().numpy()
+    assert not np.isfinite(a).all()
+    # the plan is unharmed: a finite sinogram afterwards gives the usual result
+    y[37, 61] = 0.0
+    a2 = plan.adjoint(to_dev(y)).cpu().numpy()
+    assert rel(a2, grid_adjoint(y.astype(np.float64), uniform_angles(nv), n)) < TOL_GRID
+
+
+def test_split_strips_repeat_bitwise():
+    """Split strips (the dense centre) are summed by their last item in slot
+    order: many repeated adjoints, interleaved with other plans' work, give
+    the same bits."""
+    note("split-strip sums, repeated")
+    n, nv = 256, 360
+    plan = Plan(n, uniform_angles(nv), n)
+    other = Plan(64, uniform_angles(30), 64)
+    assert plan.info()["n_slots"] > 0
+    y = to_dev(random_sinogram(94, nv, n))
+    y2 = to_dev(random_sinogram(95, 30, 64))
+    a0 = plan.adjoint(y).clone()
+    for _ in range(8):
+        other.adjoint(y2)
+        assert torch.equal(plan.adjoint(y), a0)
+    assert rel(a0.cpu().numpy(), grid_adjoint(y.cpu().numpy().astype(np.float64), uniform_angles(nv), n)) < TOL_GRID
