@@ -106,9 +106,11 @@ radon_status_t radon_plan_tuning(radon_plan_t plan, radon_tuning* out);
  * (after one untimed pair) of candidate decompositions on `stream`, by
  * coordinate search from the defaults: the tile size over {8, 16, 32} (those
  * that fit), then a2_chunk over {256, 512}, then f3_chunk over {1024, 2048,
- * 4096}, each step keeping the fastest so far. Returns the fastest in *best
- * with its time per pair in *best_ms; *default_ms (may be NULL) gets the time
- * of the default decomposition. Inputs are generated on the device; the
+ * 4096}. A candidate replaces the best so far only when it is faster by more
+ * than the run-to-run spread: the two are timed three times, interleaved, and
+ * the candidate's least time must be 3% below the best's. Returns the chosen
+ * decomposition in *best with its least time per pair in *best_ms;
+ * *default_ms (may be NULL) gets the time of the default decomposition. Inputs are generated on the device; the
  * plans and buffers are released before returning. Synchronises the stream.
  * Errors in the geometry are reported as by radon_plan.
  */
@@ -144,14 +146,20 @@ radon_status_t radon_adjoint_batched(radon_plan_t plan, int batch, const float* 
 
 /*
  * Batches of uneven slices: `count` plans of any sizes (distinct plan objects,
- * each used by this batch only while it runs) applied together. The first
- * call for a given set of device pointers records every slice's kernels into
- * one HIP graph, the slices dealt round-robin over `n_branches` independent
- * branches (1..16) so that small slices run side by side; later calls with
- * the same pointers replay the graph with a single launch on `stream`. New
- * pointers record a new graph. imgs_dev[i] is plan i's n*n image,
- * sinos_dev[i] its n_views*n_det sinogram. Profiling must be off on every
- * plan. The batch keeps the plan handles: destroy it before them.
+ * each used by this batch only while it runs) applied together, each pass of
+ * the path once for all slices (the paper balances the gridding over thread
+ * blocks by bins, section "fast radon transform", paragraph 4; here the bins
+ * of all slices share one work list). Per direction the batch launches one
+ * kernel per pass and FFT length for the transforms and one per (kernel
+ * width, tile size) for the gridding, whose items from every slice are
+ * drained longest first. The first call for a given set of device pointers
+ * records these launches into one HIP graph (the launches of different
+ * lengths on up to `n_branches` parallel branches, 1..16); later calls with
+ * the same pointers replay it with one graph launch on `stream`. New pointers
+ * record a new graph. Every slice's result equals its per-slice call bit for
+ * bit. imgs_dev[i] is plan i's n*n image, sinos_dev[i] its n_views*n_det
+ * sinogram. Profiling must be off on every plan. The batch keeps the plan
+ * handles: destroy it before them.
  */
 typedef struct radon_batch_s* radon_batch_t;
 radon_status_t radon_batch_create(radon_batch_t* out, int count, const radon_plan_t* plans, int n_branches);

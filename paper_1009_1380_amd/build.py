@@ -25,6 +25,11 @@ ARCH = "gfx950"
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add fusion: every floating-point operation rounds
+    # the same way in whichever kernel a shared body is inlined into, so the
+    # batch kernels reproduce the single-slice kernels bit for bit (fused
+    # multiply-adds are written out where they are wanted)
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 

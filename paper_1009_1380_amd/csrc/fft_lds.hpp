@@ -34,8 +34,11 @@ __device__ __forceinline__ void lds_sync() {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Complex product with its two fused multiply-adds written out (the library
+// is built without implicit contraction, so the rounding is the same in every
+// kernel that uses it).
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
@@ -60,7 +63,7 @@ template <> struct Dft<3> {
         const float s3 = 0.86602540378443865f;  // sin(2 pi / 3)
         float2 t = cadd(v[1], v[2]);
         float2 d = csub(v[1], v[2]);
-        float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
+        float2 m = make_float2(fmaf(-0.5f, t.x, v[0].x), fmaf(-0.5f, t.y, v[0].y));
         float2 r = mul_mi(cscale(d, s3));       // -i s3 (v1 - v2)
         v[0] = cadd(v[0], t);
         v[1] = cadd(m, r);
@@ -87,10 +90,10 @@ template <> struct Dft<5> {
         const float s2 = 0.58778525229247313f;   // sin(4 pi / 5)
         float2 t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
         float2 t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
-        float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
-        float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
-        float2 b1 = mul_mi(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
-        float2 b2 = mul_mi(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+        float2 a1 = make_float2(fmaf(c2, t2.x, fmaf(c1, t1.x, v[0].x)), fmaf(c2, t2.y, fmaf(c1, t1.y, v[0].y)));
+        float2 a2 = make_float2(fmaf(c1, t2.x, fmaf(c2, t1.x, v[0].x)), fmaf(c1, t2.y, fmaf(c2, t1.y, v[0].y)));
+        float2 b1 = mul_mi(make_float2(fmaf(s2, d2.x, s1 * d1.x), fmaf(s2, d2.y, s1 * d1.y)));
+        float2 b2 = mul_mi(make_float2(fmaf(-s1, d2.x, s2 * d1.x), fmaf(-s1, d2.y, s2 * d1.y)));
         v[0] = cadd(v[0], cadd(t1, t2));
         v[1] = cadd(a1, b1);
         v[4] = csub(a1, b1);

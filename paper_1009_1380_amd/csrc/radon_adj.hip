@@ -98,4 +98,68 @@ hipError_t launch_a4(const Plan& p, float* img, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- batches
+
+hipError_t launch_pass_adj(PassKind kind, int len, const PassSlice* tab, int ns, int nblocks, hipStream_t st) {
+    if (ns <= 0 || nblocks <= 0) return hipSuccess;
+    switch (len) {
+#define RN_CASE(L)                                                                                         \
+    case L:                                                                                                \
+        switch (kind) {                                                                                    \
+            case PK_A1:                                                                                    \
+                hipLaunchKernelGGL((k_a1_multi<L, ray_threads(L)>), dim3(nblocks), dim3(ray_threads(L)),   \
+                                   0, st, tab, ns);                                                        \
+                break;                                                                                     \
+            case PK_A3:                                                                                    \
+                hipLaunchKernelGGL((k_a3_multi<L, col_threads(L)>), dim3(nblocks), dim3(col_threads(L)),   \
+                                   0, st, tab, ns);                                                        \
+                break;                                                                                     \
+            case PK_A4:                                                                                    \
+                hipLaunchKernelGGL((k_a4_multi<L, row_threads(L)>), dim3(nblocks), dim3(row_threads(L)),   \
+                                   0, st, tab, ns);                                                        \
+                break;                                                                                     \
+            default:                                                                                       \
+                return hipErrorInvalidValue;                                                               \
+        }                                                                                                  \
+        break;
+        RN_FOR_LENGTHS(RN_CASE)
+#undef RN_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int W, int T>
+static hipError_t launch_a2m_wt(const GridLaunch& g, const GridSlice* gs, bool reduce, hipStream_t st) {
+    if (!reduce) {
+        if (g.n_items == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_a2_multi<W, T>), dim3(g.n_items), dim3(A2_NT), 0, st, g.items, gs, g.kbc);
+    } else {
+        if (g.n_splits == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_a2r_multi<T>), dim3(g.n_splits, (A2_GX * T * T + 255) / 256), dim3(256), 0, st,
+                           g.splits, gs);
+    }
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t launch_a2m_w(const GridLaunch& g, const GridSlice* gs, bool reduce, hipStream_t st) {
+    switch (g.T) {
+        case 8: return launch_a2m_wt<W, 8>(g, gs, reduce, st);
+        case 16: return launch_a2m_wt<W, 16>(g, gs, reduce, st);
+        case 32: return launch_a2m_wt<W, 32>(g, gs, reduce, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_a2_grid(const GridLaunch& g, const GridSlice* gs, bool reduce, hipStream_t st) {
+    switch (g.W) {
+        case 4: return launch_a2m_w<4>(g, gs, reduce, st);
+        case 6: return launch_a2m_w<6>(g, gs, reduce, st);
+        case 8: return launch_a2m_w<8>(g, gs, reduce, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace rn

@@ -341,7 +341,7 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
                 items.push_back({cx, cy, 0, total, -1, gx, 0, 0});
             } else {
                 const int nch = (total + chunk - 1) / chunk;
-                splits.push_back({cx, cy, slots, nch, gx});
+                splits.push_back({cx, cy, slots, nch, gx, 0});
                 for (int k = 0; k < nch; ++k)
                     items.push_back({cx, cy, k * chunk, std::min(chunk, total - k * chunk), slots + k, gx, 0, 0});
                 slots += nch;
@@ -374,13 +374,16 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
                      [](const rn::F3Item& a, const rn::F3Item& b) { return a.count > b.count; });
     p.n_items = (int)items.size();
     p.n_fitems = (int)fitems.size();
+    p.items_h = items;
+    p.fitems_h = fitems;
+    p.splits_h = splits;
     {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p.device) != hipSuccess || cus < 1) {
             (void)hipGetLastError();
             cus = 1;
         }
-        p.f3_grid = std::max(1, std::min(p.n_fitems, rn::f3_blocks_per_cu(p) * cus));
+        p.f3_grid = std::max(1, std::min(p.n_fitems, rn::f3_blocks_per_cu(p.W, p.T) * cus));
     }
     p.n_splits = (int)splits.size();
     p.n_slots = slots;

@@ -3,16 +3,19 @@
 //
 // Parallel-beam tomography reconstructs every slice of a volume on its own
 // (introduction: slices of the imaged samples), and slices differ in size and
-// view count. A batch records the forward (or adjoint) kernel sequences of
-// all its slices into one HIP graph: the slices are dealt round-robin over
-// independent branches, so the small slices, whose kernels cannot fill the
-// device alone, run side by side, and the whole batch is one graph launch
-// instead of nine kernel launches per slice.
+// view count. A batch runs each pass of the path once for all its slices
+// (radon_multi.hpp): one launch per pass and FFT length for the transforms,
+// one launch per kernel width and tile size for the gridding, whose work
+// items from every slice form one list drained longest first (the paper's
+// balancing of bins over thread blocks, section "fast radon transform",
+// paragraph 4, across slices). The launches of one direction are recorded
+// once into a HIP graph (launches for different lengths on parallel
+// branches) and replayed with one graph launch.
 //
-// The autotuner revisits the paper's load-balancing choice of bins (section
-// "fast radon transform", paragraph 4: the work of a bin grows with its
-// samples times its grid points) by measurement: it times each candidate
-// decomposition of the same geometry on the device and keeps the fastest.
+// The autotuner revisits the paper's load-balancing choice of bins (the work
+// of a bin grows with its samples times its grid points) by measurement: it
+// times each candidate decomposition of the same geometry on the device and
+// keeps the fastest.
 #include <stdarg.h>
 #include <stdio.h>
 
@@ -29,9 +32,14 @@ struct Recording {
     std::vector<const void*> in, out;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    rn::PassSlice* tab = nullptr;   // the transform passes' slice tables (device)
+    std::vector<void*> owned;
     void release() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        for (void* p : owned) (void)hipFree(p);
+        owned.clear();
+        tab = nullptr;
         exec = nullptr;
         graph = nullptr;
         in.clear();
@@ -65,56 +73,231 @@ __global__ void k_fill_hash(float* __restrict__ x, size_t n, unsigned seed) {
 
 }  // namespace
 
+namespace {
+
+using rn::GridSlice;
+using rn::PassKind;
+using rn::PassSlice;
+
+// Slices that share a kernel width and tile size: their gridding work items,
+// concatenated (each naming its slice) and ordered longest first.
+struct GridGroup {
+    rn::GridLaunch launch{};
+};
+
+template <class T>
+bool upload_vec(std::vector<void*>& owned, T** dst, const std::vector<T>& v) {
+    *dst = nullptr;
+    if (v.empty()) return true;
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, sizeof(T) * v.size()) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    owned.push_back(ptr);
+    if (hipMemcpy(ptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    *dst = static_cast<T*>(ptr);
+    return true;
+}
+
+}  // namespace
+
 struct radon_batch_s {
     int device = 0;
     std::vector<radon_plan_t> plans;
     std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> events;   // [0] fork, [1..] joins
+    std::vector<hipEvent_t> events;   // 4 per branch: two forks and two joins per direction
     Recording fwd, adj;
     int recorded = 0;
+    // launch structure, fixed at creation
+    std::vector<int> lengths_n, lengths_nd;            // distinct image sizes / detector counts
+    std::vector<GridGroup> groups;                     // distinct (W, T)
+    GridSlice* gs = nullptr;                           // per slice gridding buffers (device)
+    std::vector<void*> owned;                          // device buffers of the lists above
 
     ~radon_batch_s() {
         fwd.release();
         adj.release();
+        for (void* p : owned) (void)hipFree(p);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (hipStream_t s : streams) (void)hipStreamDestroy(s);
     }
 
-    // Record every slice's sequence (forward or adjoint) into rec's graph.
+    // Group the slices and upload the gridding lists (once per batch).
+    radon_status_t build() {
+        const int P = (int)plans.size();
+        std::vector<GridSlice> gsh(P);
+        for (int i = 0; i < P; ++i) {
+            const rn::Plan& p = plans[i]->p;
+            gsh[i] = rn::grid_slice_of(p);
+            if (std::find(lengths_n.begin(), lengths_n.end(), p.n) == lengths_n.end()) lengths_n.push_back(p.n);
+            if (std::find(lengths_nd.begin(), lengths_nd.end(), p.n_det) == lengths_nd.end())
+                lengths_nd.push_back(p.n_det);
+        }
+        std::sort(lengths_n.begin(), lengths_n.end());
+        std::sort(lengths_nd.begin(), lengths_nd.end());
+        if (!upload_vec(owned, &gs, gsh)) return errf(RADON_ERR_OOM, "batch table upload failed");
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) {
+            (void)hipGetLastError();
+            cus = 1;
+        }
+        std::vector<std::pair<int, int>> wts;
+        for (int i = 0; i < P; ++i) {
+            const std::pair<int, int> wt{plans[i]->p.W, plans[i]->p.T};
+            if (std::find(wts.begin(), wts.end(), wt) == wts.end()) wts.push_back(wt);
+        }
+        for (const auto& wt : wts) {
+            rn::GridLaunch g{};
+            g.W = wt.first;
+            g.T = wt.second;
+            std::vector<rn::F3Item> fi;
+            std::vector<rn::TileItem> ti;
+            std::vector<rn::SplitTile> sp;
+            for (int i = 0; i < P; ++i) {
+                const rn::Plan& p = plans[i]->p;
+                if (p.W != g.W || p.T != g.T) continue;
+                if (!g.kbc) g.kbc = p.kbc;   // the same table for every slice of one W
+                for (rn::F3Item it : p.fitems_h) { it.plan = i; fi.push_back(it); }
+                for (rn::TileItem it : p.items_h) { it.plan = i; ti.push_back(it); }
+                for (rn::SplitTile st : p.splits_h) { st.plan = i; sp.push_back(st); }
+            }
+            // longest first, so the tail of each launch is short
+            std::stable_sort(fi.begin(), fi.end(), [](const rn::F3Item& a, const rn::F3Item& b) { return a.count > b.count; });
+            std::stable_sort(ti.begin(), ti.end(), [](const rn::TileItem& a, const rn::TileItem& b) { return a.count > b.count; });
+            g.n_fitems = (int)fi.size();
+            g.n_items = (int)ti.size();
+            g.n_splits = (int)sp.size();
+            g.f3_grid = std::max(1, std::min(g.n_fitems, rn::f3_blocks_per_cu(g.W, g.T) * cus));
+            rn::F3Item* dfi = nullptr;
+            rn::TileItem* dti = nullptr;
+            rn::SplitTile* dsp = nullptr;
+            if (!upload_vec(owned, &dfi, fi) || !upload_vec(owned, &dti, ti) || !upload_vec(owned, &dsp, sp))
+                return errf(RADON_ERR_OOM, "batch work-list upload failed");
+            g.fitems = dfi;
+            g.items = dti;
+            g.splits = dsp;
+            groups.push_back(GridGroup{g});
+        }
+        return RADON_OK;
+    }
+
+    // The transform-pass tables of one direction for these I/O pointers: for
+    // each launch, its slices' entries; returns the launches' (kind, length,
+    // first entry, entries, blocks) in order.
+    struct PassLaunch {
+        PassKind kind;
+        int len, first, count, blocks;
+    };
+    void pass_tables(bool forward, const float* const* in, float* const* out, std::vector<PassSlice>& tab,
+                     std::vector<PassLaunch>& launches) const {
+        const int P = (int)plans.size();
+        auto add = [&](PassKind kind, int len) {
+            PassLaunch L{kind, len, (int)tab.size(), 0, 0};
+            const bool by_n = kind == rn::PK_F1 || kind == rn::PK_F2 || kind == rn::PK_A3 || kind == rn::PK_A4;
+            for (int i = 0; i < P; ++i) {
+                const rn::Plan& p = plans[i]->p;
+                if ((by_n ? p.n : p.n_det) != len) continue;
+                PassSlice e = rn::pass_slice_of(p, kind, in[i], out[i]);
+                e.block0 = L.blocks;
+                L.blocks += e.nblk;
+                tab.push_back(e);
+            }
+            L.count = (int)tab.size() - L.first;
+            launches.push_back(L);
+        };
+        if (forward) {
+            for (int L : lengths_n) add(rn::PK_F1, L);
+            for (int L : lengths_n) add(rn::PK_F2, L);
+            for (int L : lengths_nd) add(rn::PK_F4, L);
+        } else {
+            for (int L : lengths_nd) add(rn::PK_A1, L);
+            for (int L : lengths_n) add(rn::PK_A3, L);
+            for (int L : lengths_n) add(rn::PK_A4, L);
+        }
+    }
+
+    // Record one direction for these I/O pointers into rec's graph:
+    //   forward: F1 -> F2 per image size (one branch each), F3 per (W, T), F4 per detector count
+    //   adjoint: A1 per detector count, A2 (+ split sums) per (W, T), A3 -> A4 per image size
     radon_status_t record(bool forward, const float* const* in, float* const* out, Recording& rec) {
         rec.release();
+        std::vector<PassSlice> tab;
+        std::vector<PassLaunch> launches;
+        pass_tables(forward, in, out, tab, launches);
+        if (!upload_vec(rec.owned, &rec.tab, tab)) return errf(RADON_ERR_OOM, "batch table upload failed");
         const int nb = (int)streams.size();
         hipStream_t s0 = streams[0];
         if (hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             (void)hipGetLastError();
             return errf(RADON_ERR_DEVICE, "graph capture could not start");
         }
-        radon_status_t st = RADON_OK;
-        hipError_t e = hipEventRecord(events[0], s0);
-        for (int b = 1; b < nb && e == hipSuccess; ++b) e = hipStreamWaitEvent(streams[b], events[0], 0);
-        for (size_t i = 0; i < plans.size() && e == hipSuccess && st == RADON_OK; ++i) {
-            rn::Plan& p = plans[i]->p;
-            hipStream_t s = streams[i % nb];
-            st = forward ? rn::api_run_forward(p, in[i], out[i], s) : rn::api_run_adjoint(p, in[i], out[i], s);
+        hipError_t e = hipSuccess;
+        int ev = 0;
+        auto fork = [&]() {
+            const hipEvent_t f = events[ev++];
+            if (e == hipSuccess) e = hipEventRecord(f, s0);
+            for (int b = 1; b < nb && e == hipSuccess; ++b) e = hipStreamWaitEvent(streams[b], f, 0);
+        };
+        auto join = [&]() {
+            for (int b = 1; b < nb; ++b) {
+                const hipEvent_t j = events[ev++];
+                if (e == hipSuccess) e = hipEventRecord(j, streams[b]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(s0, j, 0);
+            }
+        };
+        auto run = [&](const PassLaunch& L, hipStream_t s) {
+            if (e == hipSuccess && L.count > 0) e = rn::launch_pass(L.kind, L.len, rec.tab + L.first, L.count, L.blocks, s);
+        };
+        const size_t nl_n = lengths_n.size(), nl_nd = lengths_nd.size();
+        if (forward) {
+            // launches: F1 x nl_n, F2 x nl_n, F4 x nl_nd
+            fork();
+            for (size_t g = 0; g < nl_n; ++g) {
+                hipStream_t s = streams[g % nb];
+                run(launches[g], s);
+                run(launches[nl_n + g], s);
+            }
+            join();
+            for (const GridGroup& g : groups)
+                if (e == hipSuccess) e = rn::launch_f3_grid(g.launch, gs, s0);
+            fork();
+            for (size_t g = 0; g < nl_nd; ++g) run(launches[2 * nl_n + g], streams[g % nb]);
+            join();
+        } else {
+            // launches: A1 x nl_nd, A3 x nl_n, A4 x nl_n
+            fork();
+            for (size_t g = 0; g < nl_nd; ++g) run(launches[g], streams[g % nb]);
+            join();
+            for (const GridGroup& g : groups) {
+                if (e == hipSuccess) e = rn::launch_a2_grid(g.launch, gs, false, s0);
+                if (e == hipSuccess) e = rn::launch_a2_grid(g.launch, gs, true, s0);
+            }
+            fork();
+            for (size_t g = 0; g < nl_n; ++g) {
+                hipStream_t s = streams[g % nb];
+                run(launches[nl_nd + g], s);
+                run(launches[nl_nd + nl_n + g], s);
+            }
+            join();
         }
-        for (int b = 1; b < nb && e == hipSuccess; ++b) {
-            e = hipEventRecord(events[b], streams[b]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(s0, events[b], 0);
-        }
-        hipGraph_t g = nullptr;
-        const hipError_t ec = hipStreamEndCapture(s0, &g);
-        if (st != RADON_OK || e != hipSuccess || ec != hipSuccess || !g) {
+        hipGraph_t gr = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s0, &gr);
+        if (e != hipSuccess || ec != hipSuccess || !gr) {
             (void)hipGetLastError();
-            if (g) (void)hipGraphDestroy(g);
-            return st != RADON_OK ? st : errf(RADON_ERR_DEVICE, "graph capture failed");
+            if (gr) (void)hipGraphDestroy(gr);
+            return errf(RADON_ERR_DEVICE, "graph capture failed");
         }
         hipGraphExec_t x = nullptr;
-        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        if (hipGraphInstantiate(&x, gr, nullptr, nullptr, 0) != hipSuccess) {
             (void)hipGetLastError();
-            (void)hipGraphDestroy(g);
+            (void)hipGraphDestroy(gr);
             return errf(RADON_ERR_DEVICE, "graph instantiation failed");
         }
-        rec.graph = g;
+        rec.graph = gr;
         rec.exec = x;
         rec.in.assign(in, in + plans.size());
         rec.out.assign(out, out + plans.size());
@@ -176,19 +359,26 @@ radon_status_t radon_batch_create(radon_batch_t* out, int count, const radon_pla
     const int nb = std::min(n_branches, count);
     for (int i = 0; i < nb; ++i) {
         hipStream_t s = nullptr;
-        hipEvent_t e = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
             delete b;
             return errf(RADON_ERR_DEVICE, "stream creation failed");
         }
         b->streams.push_back(s);
+    }
+    for (int i = 0; i < 2 * nb; ++i) {   // per direction: two forks and two joins
+        hipEvent_t e = nullptr;
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
             (void)hipGetLastError();
             delete b;
             return errf(RADON_ERR_DEVICE, "event creation failed");
         }
         b->events.push_back(e);
+    }
+    const radon_status_t st = b->build();
+    if (st != RADON_OK) {
+        delete b;
+        return st;
     }
     *out = b;
     return rn::api_ok();
@@ -277,21 +467,35 @@ radon_status_t radon_autotune(int n, const double* angles, int n_views, int n_de
     };
 
     // coordinate search: tile size first, then the spreading chunk, then the
-    // forward chunk, each with the others at their current best
+    // forward chunk, each with the others at their current best. A candidate
+    // replaces the current best only if it is faster by more than the
+    // run-to-run spread: both are timed three times, interleaved, and the
+    // candidate's best time must beat the current's best by 3%.
     radon_tuning cur = def;
     double cur_ms = 0.0;
     if ((s = time_one(cur, &cur_ms)) != RADON_OK) { cleanup(); return s; }
     if (default_ms) *default_ms = cur_ms;
     const int tiles[] = {8, 16, 32}, a2s[] = {256, 512}, f3s[] = {1024, 2048, 4096};
+    constexpr double kMargin = 0.97;
     auto try_set = [&](radon_tuning cand) -> radon_status_t {
         if (cand.tile == cur.tile && cand.a2_chunk == cur.a2_chunk && cand.f3_chunk == cur.f3_chunk) return RADON_OK;
-        double ms = 0.0;
-        const radon_status_t r = time_one(cand, &ms);
-        if (r == RADON_OK && ms > 0.0 && ms < cur_ms) {
-            cur = cand;
-            cur_ms = ms;
+        double best_c = 1e300, best_cur = 1e300;
+        for (int k = 0; k < 3; ++k) {
+            double mc = 0.0, mk = 0.0;
+            radon_status_t r = time_one(cand, &mc);
+            if (r != RADON_OK) return r;
+            if (mc < 0.0) return RADON_OK;   // the candidate does not fit this geometry
+            if ((r = time_one(cur, &mk)) != RADON_OK) return r;
+            best_c = std::min(best_c, mc);
+            best_cur = std::min(best_cur, mk);
         }
-        return r;
+        if (best_c < kMargin * best_cur) {
+            cur = cand;
+            cur_ms = best_c;
+        } else {
+            cur_ms = best_cur;
+        }
+        return RADON_OK;
     };
     for (int t : tiles) {
         radon_tuning c = cur;

@@ -1,6 +1,7 @@
 // radon_fwd.hip - launchers of the forward path (F1 row FFT, F2 column FFT,
 // F3 tiled polar interpolation, F4 ray inverse FFT), dispatched on the FFT
-// length, kernel width and tile size.
+// length, kernel width and tile size: for one slice, and for every slice of
+// an uneven batch (radon_multi.hpp).
 #include "radon_internal.hpp"
 
 namespace rn {
@@ -69,11 +70,11 @@ static int f3_occupancy_w(int T) {
     }
 }
 
-int f3_blocks_per_cu(const Plan& p) {
-    switch (p.W) {
-        case 4: return f3_occupancy_w<4>(p.T);
-        case 6: return f3_occupancy_w<6>(p.T);
-        case 8: return f3_occupancy_w<8>(p.T);
+int f3_blocks_per_cu(int W, int T) {
+    switch (W) {
+        case 4: return f3_occupancy_w<4>(T);
+        case 6: return f3_occupancy_w<6>(T);
+        case 8: return f3_occupancy_w<8>(T);
         default: return 1;
     }
 }
@@ -113,6 +114,89 @@ hipError_t launch_f4(const Plan& p, float* sino, hipStream_t st) {
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batches
+
+hipError_t launch_pass_fwd(PassKind kind, int len, const PassSlice* tab, int ns, int nblocks, hipStream_t st) {
+    if (ns <= 0 || nblocks <= 0) return hipSuccess;
+    switch (len) {
+#define RN_CASE(L)                                                                                         \
+    case L:                                                                                                \
+        switch (kind) {                                                                                    \
+            case PK_F1:                                                                                    \
+                hipLaunchKernelGGL((k_f1_multi<L, row_threads(L)>), dim3(nblocks), dim3(row_threads(L)),   \
+                                   0, st, tab, ns);                                                        \
+                break;                                                                                     \
+            case PK_F2:                                                                                    \
+                hipLaunchKernelGGL((k_f2_multi<L, col_threads(L)>), dim3(nblocks), dim3(col_threads(L)),   \
+                                   0, st, tab, ns);                                                        \
+                break;                                                                                     \
+            case PK_F4:                                                                                    \
+                hipLaunchKernelGGL((k_f4_multi<L, ray_threads(L)>), dim3(nblocks), dim3(ray_threads(L)),   \
+                                   0, st, tab, ns);                                                        \
+                break;                                                                                     \
+            default:                                                                                       \
+                return hipErrorInvalidValue;                                                               \
+        }                                                                                                  \
+        break;
+        RN_FOR_LENGTHS(RN_CASE)
+#undef RN_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(PassKind kind, int len, const PassSlice* tab, int ns, int nblocks, hipStream_t st) {
+    if (kind == PK_F1 || kind == PK_F2 || kind == PK_F4) return launch_pass_fwd(kind, len, tab, ns, nblocks, st);
+    return launch_pass_adj(kind, len, tab, ns, nblocks, st);
+}
+
+PassSlice pass_slice_of(const Plan& p, PassKind kind, const void* in, void* out) {
+    PassSlice e{};
+    e.block0 = 0;
+    e.n_views = p.n_views;
+    e.psi_inv = p.psi_inv;
+    e.shift = p.shift_n;
+    e.wq = nullptr;
+    switch (kind) {
+        case PK_F1: e.nblk = (p.n + 3) / 4; e.in = in; e.out = p.T1; e.tw = p.tw_n; break;
+        case PK_F2: e.nblk = p.n + 1; e.in = p.T1; e.out = p.grid; e.tw = p.tw_n; break;
+        case PK_F4: e.nblk = (p.n_views + 1) / 2; e.in = p.Xr; e.out = out; e.tw = p.tw_N; break;
+        case PK_A1: e.nblk = (p.n_views + 1) / 2; e.in = in; e.out = p.Yh; e.tw = p.tw_N; break;
+        case PK_A3: e.nblk = p.n + 1; e.in = p.grid; e.out = p.T1; e.tw = p.tw_n; break;
+        case PK_A4: e.nblk = (p.n + 3) / 4; e.in = p.T1; e.out = out; e.tw = p.tw_n; break;
+    }
+    return e;
+}
+
+GridSlice grid_slice_of(const Plan& p) { return GridSlice{p.offs4, p.recs, p.grid, p.Xr, p.Yh, p.partials, p.G, 0}; }
+
+template <int W, int T>
+static hipError_t launch_f3m_wt(const GridLaunch& g, const GridSlice* gs, hipStream_t st) {
+    if (g.n_fitems == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_f3_multi<W, T, 512>), dim3(g.f3_grid), dim3(512), 0, st, g.fitems, g.n_fitems, gs, g.kbc);
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t launch_f3m_w(const GridLaunch& g, const GridSlice* gs, hipStream_t st) {
+    switch (g.T) {
+        case 8: return launch_f3m_wt<W, 8>(g, gs, st);
+        case 16: return launch_f3m_wt<W, 16>(g, gs, st);
+        case 32: return launch_f3m_wt<W, 32>(g, gs, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_f3_grid(const GridLaunch& g, const GridSlice* gs, hipStream_t st) {
+    switch (g.W) {
+        case 4: return launch_f3m_w<4>(g, gs, st);
+        case 6: return launch_f3m_w<6>(g, gs, st);
+        case 8: return launch_f3m_w<8>(g, gs, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace rn

@@ -9,6 +9,7 @@
 
 #include "../../include/radon.h"
 #include "radon_kernels.hpp"
+#include "radon_multi.hpp"
 
 // Supported FFT lengths (image size n and detector count n_det).
 #define RN_FOR_LENGTHS(X)                                                                        \
@@ -68,6 +69,10 @@ struct Plan {
     TileItem* items = nullptr;
     SplitTile* splits = nullptr;
     float2* partials = nullptr;
+    // host copies of the work lists (batches concatenate them across slices)
+    std::vector<TileItem> items_h;
+    std::vector<F3Item> fitems_h;
+    std::vector<SplitTile> splits_h;
     size_t bytes = 0;
     std::vector<void*> allocs;
     int n_allocs = 0;        // device allocations made while building the plan
@@ -80,17 +85,38 @@ struct Plan {
     std::vector<hipEvent_t> event_pool;
 };
 
-// kernel launchers; each returns the launch status
+// kernel launchers of one plan; each returns the launch status
 hipError_t launch_f1(const Plan& p, const float* img, hipStream_t st);
 hipError_t launch_f2(const Plan& p, hipStream_t st);
 hipError_t launch_f3(const Plan& p, hipStream_t st);
-int f3_blocks_per_cu(const Plan& p);   // resident forward-interpolation workgroups per CU
+int f3_blocks_per_cu(int W, int T);   // resident forward-interpolation workgroups per CU
 hipError_t launch_f4(const Plan& p, float* sino, hipStream_t st);
 hipError_t launch_a1(const Plan& p, const float* sino, bool filtered, hipStream_t st);
 hipError_t launch_a2(const Plan& p, hipStream_t st);
 hipError_t launch_a2_reduce(const Plan& p, hipStream_t st);
 hipError_t launch_a3(const Plan& p, hipStream_t st);
 hipError_t launch_a4(const Plan& p, float* img, hipStream_t st);
+// Launchers for uneven batches (radon_multi.hpp): one transform pass over the
+// slices of a device table, and the gridding pass of one (W, T) group.
+enum PassKind { PK_F1, PK_F2, PK_F4, PK_A1, PK_A3, PK_A4 };
+struct GridLaunch {
+    int W, T;
+    const F3Item* fitems;
+    int n_fitems, f3_grid;
+    const TileItem* items;
+    int n_items;
+    const SplitTile* splits;
+    int n_splits;
+    const float4* kbc;
+};
+PassSlice pass_slice_of(const Plan& p, PassKind kind, const void* in, void* out);
+GridSlice grid_slice_of(const Plan& p);
+hipError_t launch_pass(PassKind kind, int len, const PassSlice* tab, int ns, int nblocks, hipStream_t st);
+hipError_t launch_pass_fwd(PassKind kind, int len, const PassSlice* tab, int ns, int nblocks, hipStream_t st);
+hipError_t launch_pass_adj(PassKind kind, int len, const PassSlice* tab, int ns, int nblocks, hipStream_t st);
+hipError_t launch_f3_grid(const GridLaunch& g, const GridSlice* gs, hipStream_t st);
+hipError_t launch_a2_grid(const GridLaunch& g, const GridSlice* gs, bool reduce, hipStream_t st);
+
 hipError_t launch_fft_test(int len, int batch, int inverse, const float2* in, float2* out,
                            const float2* tw, hipStream_t st);
 

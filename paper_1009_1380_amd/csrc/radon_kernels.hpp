@@ -146,7 +146,7 @@ __device__ __forceinline__ void f1_store(float2* __restrict__ T1, const float2* 
 }
 
 template <int NL, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL)))) void k_f1_rows(const float* __restrict__ img, float2* __restrict__ T1,
+__device__ __forceinline__ void f1_body(int bid_, int nblk_, const float* __restrict__ img, float2* __restrict__ T1,
                                                const float* __restrict__ psi_inv,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
     constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
     __shared__ float2 lds[2 * LS];
     const int tid = threadIdx.x;
-    const int i0 = 4 * xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = 4 * xcd_block(bid_, nblk_);
     float2 z[PJ][2];
 #pragma unroll
     for (int c = 0; c < PJ; ++c) {
@@ -209,12 +209,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
 // the first butterflies and the results go from the last butterflies
 // straight to HBM.
 template <int NL, int NT>
-__global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, float2* __restrict__ grid,
+__device__ __forceinline__ void f2_body(int bid_, int nblk_, const float2* __restrict__ T1, float2* __restrict__ grid,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
     __shared__ float2 lds[lds_ls(NL)];
     const int tid = threadIdx.x;
-    const int mx = blockIdx.x;
+    const int mx = bid_;
     const float2* src = T1 + (size_t)mx * NL;
     float4* dst = reinterpret_cast<float4*>(grid + (size_t)mx * (2 * NL));
     using IO = FftRegIO<NL, 1, NT>;
@@ -327,7 +327,8 @@ struct TileItem {
     int count;       // number of samples / visits
     int slot;        // spreading only: -1 writes the grid, else partial slot
     int gx;          // spreading only: tile columns of the strip
-    int pad1, pad2;
+    int plan;        // batches: index of the item's plan in the batch (else 0)
+    int pad;
 };
 
 // Per-sample record in sorted order, built once per plan so that the
@@ -379,7 +380,8 @@ struct F3Item {
     int nbx;         // bins of the super-tile along u that are forward columns (1 or 2)
     int start;       // first sample of the slice within the concatenated bins
     int count;       // samples in this slice
-    int pad0, pad1, pad2;
+    int plan;        // batches: index of the item's plan in the batch (else 0)
+    int pad1, pad2;
 };
 
 // Persistent: workgroup b takes items b, b + gridDim.x, ... (the grid is the
@@ -391,24 +393,17 @@ constexpr int F3_CHUNK = 2048;   // samples per work item
 #ifndef RN_F3_WPE
 #define RN_F3_WPE 6
 #endif
+// One work item: stage the super-tile's region in `tile`, interpolate its
+// samples. `kbt` holds the kernel's cubic pieces in LDS.
 template <int W, int T, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_F3_WPE : 1))) void k_f3_tiles(const F3Item* __restrict__ items, int n_items,
-                                                const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
-                                                const float2* __restrict__ grid, const float4* __restrict__ kbc,
-                                                float2* __restrict__ Xr, int G) {
+__device__ __forceinline__ void f3_item(const F3Item& it, const int* __restrict__ offs4,
+                                        const SampleRec* __restrict__ recs, const float2* __restrict__ grid,
+                                        float2* __restrict__ Xr, int G, float2* tile, const float4* kbt, int tid) {
     constexpr int P = 2 * T + W - 1;
     constexpr int PP = P * P;
     constexpr int PE = (PP + NT - 1) / NT;            // staged points per thread
-    constexpr int NKB = (W / 2) * KB_S;
-    __shared__ float2 tile[PP];   // [lx][ly], lx along u (mx), ly along v (my)
-    __shared__ float4 kbt[NKB];
-    const int tid = threadIdx.x;
     const int ntl = G / T;
-
-    for (int e = tid; e < NKB; e += NT) kbt[e] = kbc[e];
-
-    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
-        const F3Item it = items[i];
+    {
         const int x0 = it.cx * T, y0 = it.cy * T;
         const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
         const int b0 = it.cy * ntl + it.cx, b1 = it.cy * ntl + cx1, b2 = cy1 * ntl + it.cx, b3 = cy1 * ntl + cx1;
@@ -482,12 +477,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_
 // X[-q] = conj X[q] of Xr (bins 0 and N/2 taken as real); the two real
 // outputs share one complex IFFT. Output bin d is s = d - N/2 at s mod N.
 template <int ND, int NT>
-__global__ __launch_bounds__(NT) void k_f4_rays(const float2* __restrict__ Xr, float* __restrict__ sino,
+__device__ __forceinline__ void f4_body(int bid_, int nblk_, const float2* __restrict__ Xr, float* __restrict__ sino,
                                                const float2* __restrict__ tw, int n_views) {
     constexpr int HQ = ND / 2 + 1;
     __shared__ float2 lds[lds_ls(ND)];
     const int tid = threadIdx.x;
-    const int a0 = blockIdx.x * 2;
+    const int a0 = bid_ * 2;
     const bool has_b = a0 + 1 < n_views;
     const float2* xa = Xr + (size_t)a0 * HQ;
     const float2* xb = Xr + (size_t)(a0 + 1) * HQ;
@@ -524,13 +519,13 @@ __global__ __launch_bounds__(NT) void k_f4_rays(const float2* __restrict__ Xr, f
 // table wq (the ramp of the filtered adjoint) Yhat_a[q] is multiplied by
 // wq[q]; wq = nullptr gives the plain adjoint.
 template <int ND, int NT>
-__global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, float2* __restrict__ Yh,
+__device__ __forceinline__ void a1_body(int bid_, int nblk_, const float* __restrict__ sino, float2* __restrict__ Yh,
                                                const float2* __restrict__ tw, const float* __restrict__ wq,
                                                int n_views) {
     constexpr int HQ = ND / 2 + 1;
     __shared__ float2 lds[lds_ls(ND)];
     const int tid = threadIdx.x;
-    const int a0 = blockIdx.x * 2;
+    const int a0 = bid_ * 2;
     for (int d = tid; d < ND; d += NT) {
         const float ya = (a0 < n_views) ? sino[(size_t)a0 * ND + d] : 0.f;
         const float yb = (a0 + 1 < n_views) ? sino[(size_t)(a0 + 1) * ND + d] : 0.f;
@@ -594,10 +589,10 @@ constexpr int A2_GX = RN_A2_GX;   // tile columns per strip (at most)
 #define RN_A2_WPE 6
 #endif
 template <int W, int T>
-__global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_A2_WPE : 1))) void k_a2_spread(
-    const TileItem* __restrict__ items, const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
-    const float2* __restrict__ Yh, const float4* __restrict__ kbc, float2* __restrict__ grid,
-    float2* __restrict__ partials, int G) {
+__device__ __forceinline__ void a2_item(const TileItem& it, const int* __restrict__ offs4,
+                                        const SampleRec* __restrict__ recs, const float2* __restrict__ Yh,
+                                        const float4* __restrict__ kbc, float2* __restrict__ grid,
+                                        float2* __restrict__ partials, int G) {
     constexpr int PX = A2_GX * T + 2 * (W - 1);   // accumulator: local [-(W-1), A2_GX T + W-1) along u
     constexpr int PY = T + 2 * (W - 1);           // and [-(W-1), T + W-1) along v
     constexpr int NKB = (W / 2) * KB_S;
@@ -606,7 +601,6 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
     __shared__ float4 kbt[NKB];
     __shared__ float wmax[A2_NT / 64];
     const int tid = threadIdx.x;
-    const TileItem it = items[blockIdx.x];
     const int gx = it.gx;
     const int ntl = G / T;
 
@@ -751,23 +745,22 @@ struct SplitTile {
     int cx, cy;
     int first_slot, nslots;
     int gx;          // tile columns of the strip
+    int plan;        // batches: index of the strip's plan in the batch (else 0)
 };
 
 #ifndef RN_A2R_FLIGHT
 #define RN_A2R_FLIGHT 16
 #endif
 template <int T>
-__global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__ splits,
-                                                  const float2* __restrict__ partials,
-                                                  float2* __restrict__ grid, int G) {
+__device__ __forceinline__ void a2r_body(const SplitTile& sp, int by, const float2* __restrict__ partials,
+                                         float2* __restrict__ grid, int G) {
     constexpr int SLOT = A2_GX * T * T;   // points per partial slot
-    const SplitTile sp = splits[blockIdx.x];
     const int xvalid = (sp.cx == 0) ? 1 : sp.gx * T;   // tile column 0 holds only mx = G/2
     const int x0 = sp.cx * T, y0 = sp.cy * T;
     const int my0 = mod_pos(y0 - G / 2, G);
     const float2* src = partials + (size_t)sp.first_slot * SLOT;
-    // blockIdx.y picks 256 of the strip's points, one per thread
-    for (int e = blockIdx.y * 256 + threadIdx.x; e < xvalid * T && e < (blockIdx.y + 1) * 256; e += 256) {
+    // block row `by` picks 256 of the strip's points, one per thread
+    for (int e = by * 256 + threadIdx.x; e < xvalid * T && e < (by + 1) * 256; e += 256) {
         // slots are added in order; the loads of RN_A2R_FLIGHT slots (the last batch
         // predicated) are issued together
         float2 s = make_float2(0.f, 0.f);
@@ -792,12 +785,12 @@ __global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__
 // the two inverse transforms share one LDS line, one after the other, each
 // with register input and output (FftRegIO); the inverse is conj(FFT(conj)).
 template <int NL, int NT>
-__global__ __launch_bounds__(NT) void k_a3_cols(const float2* __restrict__ grid, float2* __restrict__ T1,
+__device__ __forceinline__ void a3_body(int bid_, int nblk_, const float2* __restrict__ grid, float2* __restrict__ T1,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
     __shared__ float2 lds[lds_ls(NL)];
     const int tid = threadIdx.x;
-    const int mx = blockIdx.x;
+    const int mx = bid_;
     const float4* src = reinterpret_cast<const float4*>(grid + (size_t)mx * (2 * NL));
     float2* dst = T1 + (size_t)mx * NL;
     using IO = FftRegIO<NL, 1, NT>;
@@ -896,7 +889,7 @@ __device__ __forceinline__ void a4_load(const float2* __restrict__ T1, float2* l
 }
 
 template <int NL, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL)))) void k_a4_rows(const float2* __restrict__ T1, float* __restrict__ img,
+__device__ __forceinline__ void a4_body(int bid_, int nblk_, const float2* __restrict__ T1, float* __restrict__ img,
                                                const float* __restrict__ psi_inv,
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
@@ -904,7 +897,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
     constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
     __shared__ float2 lds[2 * LS];
     const int tid = threadIdx.x;
-    const int i0 = 4 * xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = 4 * xcd_block(bid_, nblk_);
     // even mx = 2k: position k, mirror 2n - 2k at n - k
     for (int e = tid; e < 2 * (NL / 2 + 1); e += NT) {
         const int k = e >> 1;
@@ -947,6 +940,83 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
             }
         }
     }
+}
+
+// ---------------------------------------------------------------- single-slice kernels
+// One launch per pass of one slice (batches use radon_multi.hpp's kernels,
+// which run the same bodies).
+template <int NL, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL)))) void k_f1_rows(
+    const float* __restrict__ img, float2* __restrict__ T1, const float* __restrict__ psi_inv,
+    const float2* __restrict__ shift, const float2* __restrict__ tw) {
+    f1_body<NL, NT>(blockIdx.x, gridDim.x, img, T1, psi_inv, shift, tw);
+}
+
+template <int NL, int NT>
+__global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, float2* __restrict__ grid,
+                                               const float2* __restrict__ shift, const float2* __restrict__ tw) {
+    f2_body<NL, NT>(blockIdx.x, gridDim.x, T1, grid, shift, tw);
+}
+
+// Persistent: workgroup b takes items b, b + gridDim.x, ... (the grid is the
+// number of workgroups that fit on the device at once).
+template <int W, int T, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_F3_WPE : 1))) void k_f3_tiles(
+    const F3Item* __restrict__ items, int n_items, const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
+    const float2* __restrict__ grid, const float4* __restrict__ kbc, float2* __restrict__ Xr, int G) {
+    constexpr int PP = (2 * T + W - 1) * (2 * T + W - 1);
+    constexpr int NKB = (W / 2) * KB_S;
+    __shared__ float2 tile[PP];   // [lx][ly], lx along u (mx), ly along v (my)
+    __shared__ float4 kbt[NKB];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NKB; e += NT) kbt[e] = kbc[e];
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+        const F3Item it = items[i];
+        f3_item<W, T, NT>(it, offs4, recs, grid, Xr, G, tile, kbt, tid);
+    }
+}
+
+template <int ND, int NT>
+__global__ __launch_bounds__(NT) void k_f4_rays(const float2* __restrict__ Xr, float* __restrict__ sino,
+                                               const float2* __restrict__ tw, int n_views) {
+    f4_body<ND, NT>(blockIdx.x, gridDim.x, Xr, sino, tw, n_views);
+}
+
+template <int ND, int NT>
+__global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, float2* __restrict__ Yh,
+                                               const float2* __restrict__ tw, const float* __restrict__ wq,
+                                               int n_views) {
+    a1_body<ND, NT>(blockIdx.x, gridDim.x, sino, Yh, tw, wq, n_views);
+}
+
+template <int W, int T>
+__global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_A2_WPE : 1))) void k_a2_spread(
+    const TileItem* __restrict__ items, const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
+    const float2* __restrict__ Yh, const float4* __restrict__ kbc, float2* __restrict__ grid,
+    float2* __restrict__ partials, int G) {
+    const TileItem it = items[blockIdx.x];
+    a2_item<W, T>(it, offs4, recs, Yh, kbc, grid, partials, G);
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_a2_reduce(const SplitTile* __restrict__ splits,
+                                                  const float2* __restrict__ partials, float2* __restrict__ grid,
+                                                  int G) {
+    const SplitTile sp = splits[blockIdx.x];
+    a2r_body<T>(sp, blockIdx.y, partials, grid, G);
+}
+
+template <int NL, int NT>
+__global__ __launch_bounds__(NT) void k_a3_cols(const float2* __restrict__ grid, float2* __restrict__ T1,
+                                               const float2* __restrict__ shift, const float2* __restrict__ tw) {
+    a3_body<NL, NT>(blockIdx.x, gridDim.x, grid, T1, shift, tw);
+}
+
+template <int NL, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL)))) void k_a4_rows(
+    const float2* __restrict__ T1, float* __restrict__ img, const float* __restrict__ psi_inv,
+    const float2* __restrict__ shift, const float2* __restrict__ tw) {
+    a4_body<NL, NT>(blockIdx.x, gridDim.x, T1, img, psi_inv, shift, tw);
 }
 
 // ---------------------------------------------------------------- FFT test

@@ -27,7 +27,10 @@
 namespace rn {
 
 constexpr int SV_NT = 256;           // threads per reduction block
-constexpr int SV_BLOCKS = 512;       // blocks of the grid-stride reductions
+#ifndef RN_SV_BLOCKS
+#define RN_SV_BLOCKS 512
+#endif
+constexpr int SV_BLOCKS = RN_SV_BLOCKS;   // blocks of the grid-stride reductions
 constexpr int SV_SLOTS = 8;          // partial-result slots
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -177,7 +180,10 @@ __global__ __launch_bounds__(SV_NT) void k_sv_bb(const float* __restrict__ x, co
 // in block order and takes the step, so the result is deterministic. Steps
 // after convergence return at once. State: st[0] = lam, st[1] = done flag.
 constexpr int PJ_NT = 256;
-constexpr int PJ_BLOCKS = 256;
+#ifndef RN_PJ_BLOCKS
+#define RN_PJ_BLOCKS 256
+#endif
+constexpr int PJ_BLOCKS = RN_PJ_BLOCKS;
 constexpr int PJ_STEPS = 12;   // launches per projection; the host checks the flag
 
 __global__ __launch_bounds__(PJ_NT) void k_sv_pj_step(const float* __restrict__ x, const float* __restrict__ h,
