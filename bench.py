@@ -58,16 +58,17 @@ def kernel_bytes(n: int, n_views: int, n_det: int):
 
 
 # the files that define the path's kernels and their launch shapes
-KERNEL_SOURCES = ("fft_lds.hpp", "radon_kernels.hpp", "radon_sort.hpp", "radon_fwd.hip", "radon_adj.hip", "radon_api.hip")
+KERNEL_SOURCES = ("fft_lds.hpp", "radon_kernels.hpp", "radon_multi.hpp", "radon_sort.hpp", "radon_fwd.hip",
+                  "radon_adj.hip", "radon_api.hip")
 
 
 def source_hash() -> str:
     """Hash of the kernel sources; counter-derived traffic is reported only
     while the kernels are the ones the counters were taken on."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1009_1380_amd", "csrc")
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
+    pkg = os.path.join(ROOT, "paper_1009_1380_amd")
+    for name in KERNEL_SOURCES + ("../build.py",):
+        with open(os.path.join(pkg, "csrc", name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
     return h.hexdigest()
@@ -218,7 +219,7 @@ BATCH_SIZES = (512, 1024, 1536, 2048, 2560)
 BATCH_VIEWS = (90, 180, 360, 720, 1024)
 
 
-def batch_times(dev, n_slices: int = 64, repeats: int = 5, seed: int = 0):
+def batch_times(dev, n_slices: int = 64, repeats: int = 5, seed: int = 0, tune: bool = True):
     """Uneven slices: n_slices slices, side uniform in BATCH_SIZES, view count
     uniform in BATCH_VIEWS (angles uniform in [0, pi)), detector bins = side.
     One step = forward + adjoint of every slice. Three ways: per-slice calls
@@ -265,6 +266,18 @@ def batch_times(dev, n_slices: int = 64, repeats: int = 5, seed: int = 0):
     plans = [Plan(n, uniform_angles(v), n) for n, v in shapes]
     ms_slice, ms_graph = run_modes(plans)
     del plans
+
+    def gs(ms):
+        return round(samples / (ms * 1e-3) / 1e9, 3)
+    out = {
+        "workload": f"{n_slices} uneven slices: side uniform in {list(BATCH_SIZES)}, views uniform in "
+                    f"{list(BATCH_VIEWS)}, detector bins = side; one step = forward + adjoint of every slice",
+        "samples_per_step": samples,
+        "per_slice_calls": {"ms_per_step": round(ms_slice, 3), "Gsamples_per_s": gs(ms_slice)},
+        "graph_batch": {"ms_per_step": round(ms_graph, 3), "Gsamples_per_s": gs(ms_graph)},
+    }
+    if not tune:
+        return out
     t0 = time.perf_counter()
     tuned = {}
     for n, v in sorted(set(shapes)):
@@ -275,18 +288,12 @@ def batch_times(dev, n_slices: int = 64, repeats: int = 5, seed: int = 0):
     del plans
     changed = sum(1 for k, (best, _, _) in tuned.items() if best != {"tile": 32, "a2_chunk": 512, "f3_chunk": 2048})
 
-    def gs(ms):
-        return round(samples / (ms * 1e-3) / 1e9, 3)
-    return {
-        "workload": f"{n_slices} uneven slices: side uniform in {list(BATCH_SIZES)}, views uniform in "
-                    f"{list(BATCH_VIEWS)}, detector bins = side; one step = forward + adjoint of every slice",
-        "samples_per_step": samples,
-        "per_slice_calls": {"ms_per_step": round(ms_slice, 3), "Gsamples_per_s": gs(ms_slice)},
-        "graph_batch": {"ms_per_step": round(ms_graph, 3), "Gsamples_per_s": gs(ms_graph)},
+    out.update({
         "per_slice_calls_autotuned": {"ms_per_step": round(ms_slice_t, 3), "Gsamples_per_s": gs(ms_slice_t)},
         "graph_batch_autotuned": {"ms_per_step": round(ms_graph_t, 3), "Gsamples_per_s": gs(ms_graph_t)},
         "autotune": {"seconds": round(t_tune, 2), "shapes": len(tuned), "shapes_off_default": changed},
-    }
+    })
+    return out
 
 
 def warmstart_times(pairs: int = 256, epochs: int = 4, n_eval: int = 20):
@@ -326,6 +333,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the reduced-view solve timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-slice batch timing")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start run")
+    ap.add_argument("--no-autotune", action="store_true", help="batch timing without the autotuned half")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -499,7 +507,7 @@ def main():
         line["solve"] = solve_times(dev)
     if not args.no_batch:
         print("bench: timing the uneven-slice batch", file=sys.stderr, flush=True)
-        line["batch"] = batch_times(dev)
+        line["batch"] = batch_times(dev, tune=not args.no_autotune)
     if not args.no_warmstart:
         print("bench: learned warm start (reduced)", file=sys.stderr, flush=True)
         line["warmstart"] = warmstart_times()

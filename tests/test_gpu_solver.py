@@ -54,14 +54,13 @@ def _problem(n=32, nv=24, seed=0):
     return x, ang, b.astype(np.float32)
 
 
-@pytest.mark.parametrize("ring", [True, False])
-def test_solver_matches_oracle(ring):
-    note(f"solver ring={ring}")
-    n, nv = 32, 24
-    x_true, ang, b = _problem(n, nv)
+@pytest.mark.parametrize("ring,n,nv,seed", [(True, 32, 24, 0), (False, 32, 24, 0), (True, 64, 48, 3)])
+def test_solver_matches_oracle(ring, n, nv, seed):
+    note(f"solver ring={ring} n={n} views={nv}")
+    x_true, ang, b = _problem(n, nv, seed)
     F = ring_filter if ring else (lambda v: v)
     bt = F(b.astype(np.float64))
-    sigma = 0.05 * float(np.linalg.norm(bt))
+    sigma = (0.05 if n == 32 else 0.03) * float(np.linalg.norm(bt))
     A = lambda v: F(grid_forward(v, ang, n))            # noqa: E731
     At = lambda r: grid_adjoint(F(r), ang, n)           # noqa: E731
     xo, io = spgl1_bpdn(A, At, bt, sigma, opt_tol=1e-5, max_iter=5000)
