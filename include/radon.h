@@ -71,7 +71,11 @@ typedef enum {
  * Kaiser-Bessel table and deapodization factors in float64 (rounded once
  * to float32), sorts the polar samples by footprint tile on the device, and
  * allocates its workspace. It synchronises the device before returning.
- * On failure *out is set to NULL. Release with radon_plan_destroy.
+ * On failure *out is set to NULL and nothing stays allocated. Release with
+ * radon_plan_destroy.
+ * Test hook: with the environment variable RADON_TEST_FAIL_ALLOC=k, the k-th
+ * device allocation made while building a plan (counting from 1) fails as if
+ * the device were out of memory (RADON_ERR_OOM).
  */
 radon_status_t radon_plan(radon_plan_t* out, int n, const double* angles, int n_views,
                           int n_det, double sigma, int W);

@@ -471,3 +471,34 @@ def test_split_strips_repeat_bitwise():
         other.adjoint(y2)
         assert torch.equal(plan.adjoint(y), a0)
     assert rel(a0.cpu().numpy(), grid_adjoint(y.cpu().numpy().astype(np.float64), uniform_angles(nv), n)) < TOL_GRID
+
+
+def test_adjoint_grid_high_dynamic_range():
+    """The spreading's fixed-point scale is chosen per work item, from that
+    item's own largest contribution. Ten views (in pairs, so no ray transform
+    mixes a large and a small ray) are scaled by 1e6; grid regions that only
+    the other views reach must still match the oracle to float32 accuracy
+    relative to their own magnitude (a scale shared by all items would round
+    them to about 2^-22 of the large views, i.e. errors of order 1e-1 there)."""
+    note("adjoint grid, high dynamic range")
+    n, n_det, nv = 128, 128, 180
+    ang = uniform_angles(nv)
+    y = random_sinogram(96, nv, n_det).astype(np.float64)
+    y[:10] *= 1e6
+    y32 = y.astype(np.float32)
+    plan = Plan(n, ang, n_det)
+    g = plan.debug_adjoint_grid(to_dev(y32)).cpu().numpy()
+    gp = GridParams(n, n_det)
+    G = gp.G
+    u, v = polar_uv(ang, n_det, G)
+    H = grid_spread(ray_spectrum(y32.astype(np.float64), n_det), u, v, gp)
+    idx = (-np.arange(G)) % G
+    ref = (0.5 * (H + np.conj(H[np.ix_(idx, idx)])))[:, : G // 2 + 1].T     # [mx][my]
+    # the large views (angles below 9 degrees) lie within |v| <= 0.16 |u| + 3 of the u axis;
+    # rows |v| >= G/4 are two tiles away from every item those views reach
+    my = (np.arange(G) + G // 2) % G - G // 2
+    far = np.abs(my) >= G // 4
+    assert rel(g, ref) < TOL_GRID
+    err_far = np.linalg.norm(g[:, far] - ref[:, far]) / np.linalg.norm(ref[:, far])
+    note(f"far-region relative error {err_far:.2e}")
+    assert err_far < TOL_GRID
