@@ -60,37 +60,66 @@ __device__ double block_reduce(double v, double* sh) {
     return r;   // valid in thread 0
 }
 
-// Sum (or max) of the per-block partials of each slot, in block order.
-// ops bit k set: slot k is a max, else a sum.
+// Sum (or max) of the per-block partials of each slot, in block order:
+// every thread folds its strided share of each slot, the waves reduce
+// them, and thread s adds the wave results of slot s in wave order.
+// ops bit k set: slot k is a max, else a sum. nslots <= SV_FIN_SLOTS.
+constexpr int SV_FIN_SLOTS = 9;
 __global__ __launch_bounds__(SV_NT) void k_sv_final(const double* __restrict__ part, int nb, int nslots,
                                                    unsigned ops, double* __restrict__ out) {
-    __shared__ double sh[SV_NT / 64];
-    for (int s = 0; s < nslots; ++s) {
-        const bool mx = (ops >> s) & 1u;
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nb; b += SV_NT) {
-            const double p = part[(size_t)s * nb + b];
-            v = mx ? fmax(v, p) : v + p;
+    __shared__ double sh[SV_FIN_SLOTS][SV_NT / 64];
+    double v[SV_FIN_SLOTS];
+#pragma unroll
+    for (int s = 0; s < SV_FIN_SLOTS; ++s) v[s] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += SV_NT) {
+#pragma unroll
+        for (int s = 0; s < SV_FIN_SLOTS; ++s) {
+            if (s < nslots) {
+                const double p = part[(size_t)s * nb + b];
+                v[s] = ((ops >> s) & 1u) ? fmax(v[s], p) : v[s] + p;
+            }
         }
-        const double r = mx ? block_reduce<true>(v, sh) : block_reduce<false>(v, sh);
-        if (threadIdx.x == 0) out[s] = r;
-        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < SV_FIN_SLOTS; ++s) {
+        const double r = ((ops >> s) & 1u) ? wave_max(v[s]) : wave_sum(v[s]);
+        if (lane == 0) sh[s][wave] = r;
+    }
+    __syncthreads();
+    const int s = threadIdx.x;
+    if (s < nslots) {
+        const bool mx = (ops >> s) & 1u;
+        double r = sh[s][0];
+        for (int w = 1; w < SV_NT / 64; ++w) r = mx ? fmax(r, sh[s][w]) : r + sh[s][w];
+        out[s] = r;
     }
 }
 
 // m[d] = mean over views of (b - z)[., d] (z may be null: m = mean of b).
-// A block takes 32 detectors; its 8 thread groups sum every 8th view, and the
-// 8 group sums are added in group order.
+// A block takes 32 detectors; its 8 thread groups sum every 8th view (the
+// loads of 8 views issued before they are added, in view order), and the 8
+// group sums are added in group order.
 __global__ __launch_bounds__(256) void k_sv_colmean(const float* __restrict__ b, const float* __restrict__ z,
                                                    int nv, int N, double* __restrict__ m) {
+    constexpr int U = 8;
     __shared__ double part[8][32];
     const int dl = threadIdx.x & 31, g = threadIdx.x >> 5;
     const int d = blockIdx.x * 32 + dl;
     double s = 0.0;
     if (d < N) {
-        for (int a = g; a < nv; a += 8) {
-            const size_t i = (size_t)a * N + d;
-            s += (double)b[i] - (z ? (double)z[i] : 0.0);
+        for (int a0 = g; a0 < nv; a0 += 8 * U) {
+            float bv[U], zv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int a = a0 + 8 * u;
+                const size_t i = (size_t)a * N + d;
+                bv[u] = a < nv ? b[i] : 0.0f;
+                zv[u] = (z && a < nv) ? z[i] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (a0 + 8 * u < nv) s += (double)bv[u] - (z ? (double)zv[u] : 0.0);
         }
     }
     part[g][dl] = s;
@@ -102,18 +131,34 @@ __global__ __launch_bounds__(256) void k_sv_colmean(const float* __restrict__ b,
     }
 }
 
-// ring[d] = m[d] - (Q Q^T m)[d]  (one block).
+// ring[d] = m[d] - (Q Q^T m)[d]  (one block). The four coefficients
+// c_k = sum_d Q[d][k] m[d] are accumulated together, each in the order of
+// block_reduce (per thread over d, then the waves, then the wave sums in order).
 __global__ __launch_bounds__(SV_NT) void k_sv_ringfit(const double* __restrict__ m, const double* __restrict__ Q,
                                                      int N, double* __restrict__ ring) {
-    __shared__ double sh[SV_NT / 64];
+    __shared__ double sh[4][SV_NT / 64];
     __shared__ double c[4];
-    for (int k = 0; k < 4; ++k) {
-        double v = 0.0;
-        for (int d = threadIdx.x; d < N; d += SV_NT) v += Q[(size_t)d * 4 + k] * m[d];
-        const double r = block_reduce<false>(v, sh);
-        if (threadIdx.x == 0) c[k] = r;
-        __syncthreads();
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int d = threadIdx.x; d < N; d += SV_NT) {
+        const double md = m[d];
+        const double* q = Q + (size_t)d * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += q[k] * md;
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double r = wave_sum(v[k]);
+        if (lane == 0) sh[k][wave] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        double r = sh[k][0];
+        for (int w = 1; w < SV_NT / 64; ++w) r += sh[k][w];
+        c[k] = r;
+    }
+    __syncthreads();
     for (int d = threadIdx.x; d < N; d += SV_NT) {
         const double* q = Q + (size_t)d * 4;
         ring[d] = m[d] - (q[0] * c[0] + q[1] * c[1] + q[2] * c[2] + q[3] * c[3]);
@@ -145,18 +190,47 @@ __global__ __launch_bounds__(SV_NT) void k_sv_resid(const float* __restrict__ b,
 // Barzilai-Borwein quantities with s = xn - x and y = gn - g = -(hn - h):
 // slot 0 sum s^2, slot 1 sum s y, slot 2 max |hn| (= ||gn||_inf),
 // slot 3 sum |x| of the input x (used for tau at a warm start).
+// The image-sized kernels below walk n/4 16-byte pieces (n = n_image^2 is a
+// multiple of 64), SV_U pieces of each array per thread and round, all loaded
+// before any is used: with one grid-stride element per round a thread waited
+// out one memory latency per element.
+constexpr int SV_U = 4;
+
+__device__ __forceinline__ float4 ld4(const float* __restrict__ p, size_t j, size_t n4) {
+    return j < n4 ? reinterpret_cast<const float4*>(p)[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+__device__ __forceinline__ float comp(const float4& v, int c) {
+    return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+}
+
 __global__ __launch_bounds__(SV_NT) void k_sv_bb(const float* __restrict__ x, const float* __restrict__ xn,
                                                 const float* __restrict__ h, const float* __restrict__ hn, size_t n,
                                                 double* __restrict__ part) {
     __shared__ double sh[SV_NT / 64];
     double ss = 0.0, sy = 0.0, mx = 0.0, l1 = 0.0;
-    for (size_t i = (size_t)blockIdx.x * SV_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * SV_NT) {
-        const double s = (x ? (double)xn[i] - (double)x[i] : 0.0);
-        const double y = (h ? -((double)hn[i] - (double)h[i]) : 0.0);
-        ss += s * s;
-        sy += s * y;
-        mx = fmax(mx, fabs((double)hn[i]));
-        l1 += fabs((double)xn[i]);
+    const size_t n4 = n / 4, stride = (size_t)gridDim.x * SV_NT;
+    for (size_t j0 = (size_t)blockIdx.x * SV_NT + threadIdx.x; j0 < n4; j0 += stride * SV_U) {
+        float4 xv[SV_U], xnv[SV_U], hv[SV_U], hnv[SV_U];
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+            const size_t j = j0 + u * stride;
+            xnv[u] = ld4(xn, j, n4);
+            hnv[u] = ld4(hn, j, n4);
+            xv[u] = x ? ld4(x, j, n4) : make_float4(0.f, 0.f, 0.f, 0.f);
+            hv[u] = h ? ld4(h, j, n4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double s = (x ? (double)comp(xnv[u], c) - (double)comp(xv[u], c) : 0.0);
+                const double y = (h ? -((double)comp(hnv[u], c) - (double)comp(hv[u], c)) : 0.0);
+                ss += s * s;
+                sy += s * y;
+                mx = fmax(mx, fabs((double)comp(hnv[u], c)));
+                l1 += fabs((double)comp(xnv[u], c));
+            }
+        }
     }
     double t = block_reduce<false>(ss, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -168,94 +242,288 @@ __global__ __launch_bounds__(SV_NT) void k_sv_bb(const float* __restrict__ x, co
     if (threadIdx.x == 0) part[3 * gridDim.x + blockIdx.x] = t;
 }
 
-// Projection onto the l1 ball: xn = soft(v, lam), v = x + c h, with lam the
-// root of S(lam) = sum max(|v| - lam, 0) = tau, found by Newton's method
-// started at the previous projection's root (successive projections in a
-// solve have nearby roots). S is convex, decreasing and piecewise linear:
-// from below the root the iterates increase to the exact root of the final
-// active set, and a step from above lands at or below the root (a convex
-// function lies above its tangents), so at most one step is spent above.
-// One launch per step: every block writes its partial sums, and the last
-// block to finish (an atomic ticket after a memory fence) adds the partials
-// in block order and takes the step, so the result is deterministic. Steps
-// after convergence return at once. State: st[0] = lam, st[1] = done flag.
+// Projection onto the l1 ball: xn = soft(v, lam), v = x + c h (rounded to
+// float32, as the soft threshold forms it), with lam the root of
+// S(lam) = sum max(|v| - lam, 0) = tau. S is continuous, decreasing and
+// piecewise linear with breakpoints at the values |v_i|, so the root is found
+// exactly by locating it between two consecutive values: a radix select on the
+// bit pattern u of |v| (monotone in |v| for non-negative floats), 12 + 12 + 7
+// bits in three passes. Each pass histograms the elements whose leading bits
+// match the bin chosen so far, by count and by the exact integer sum of their
+// significands (the bins of a pass share one exponent), so the histograms are
+// order-independent integers and the select is deterministic. From the counts
+// and sums above each bin edge e the last block evaluates S(e) exactly up to
+// the final float64 sums, takes the highest non-empty bin whose lower edge
+// has S >= tau, and either finishes (the root lies in an empty gap, below every
+// element in play, or the bins are single values) with
+// lam = (sum of |v| above the root - tau) / (their count), or descends into
+// that bin. Special cases: sum |v| <= tau gives lam = 0 (v is in the ball);
+// tau = 0 gives a lam at or above max |v|; a NaN or infinite v gives lam = NaN,
+// which the soft threshold turns into NaN outputs.
+// One launch per pass: every block histograms its elements in LDS, one wave
+// adds the non-empty bins to the global histogram with integer atomics and
+// takes the block's ticket after a memory fence, and the last block to finish
+// reads and clears the global histogram and decides. Passes after the
+// decision return at once.
 constexpr int PJ_NT = 256;
 #ifndef RN_PJ_BLOCKS
 #define RN_PJ_BLOCKS 256
 #endif
 constexpr int PJ_BLOCKS = RN_PJ_BLOCKS;
-constexpr int PJ_STEPS = 12;   // launches per projection; the host checks the flag
+constexpr int PJ_BINS = 4096;   // bins of the first two passes (12 bits each); the third has 128
+constexpr int PJ_PASSES = 3;
 
-__global__ __launch_bounds__(PJ_NT) void k_sv_pj_step(const float* __restrict__ x, const float* __restrict__ h,
-                                                     double c, double tau, size_t n, double* __restrict__ st,
-                                                     double* __restrict__ part, unsigned* __restrict__ ticket) {
-    __shared__ double sh[PJ_NT / 64];
+struct PjState {
+    double lam;        // the threshold, final once done != 0
+    double done;       // 1 once lam is final
+    double A, C;       // sum and count of |v| above the bin chosen so far
+    unsigned prefix;   // leading bits of u fixed by the passes so far
+    unsigned pad;
+};
+
+// v exactly as the soft threshold forms it
+__device__ __forceinline__ float pj_v(float x, float h, double c) { return (float)((double)x + c * (double)h); }
+
+template <int PASS>
+__global__ __launch_bounds__(PJ_NT) void k_sv_pj_pass(const float* __restrict__ x, const float* __restrict__ h,
+                                                     double c, double tau, size_t n, PjState* __restrict__ st,
+                                                     unsigned* __restrict__ hcnt, unsigned long long* __restrict__ hsum,
+                                                     unsigned* __restrict__ hbad, unsigned* __restrict__ ticket) {
+    constexpr int NB = PASS == 3 ? 128 : PJ_BINS;
+    constexpr int SHIFT = PASS == 1 ? 19 : PASS == 2 ? 7 : 0;   // digit = (u >> SHIFT) % NB
+    constexpr int PSHIFT = SHIFT + (PASS == 3 ? 7 : 12);          // u >> PSHIFT must equal the prefix
+    constexpr unsigned LOW = (1u << SHIFT) - 1;                    // bits below the digit
+    constexpr int CSHIFT = 40;   // LDS bin: count << 40 | sum of the bits below the digit
+    __shared__ unsigned long long lh[NB];
+    __shared__ unsigned lbad;
     __shared__ bool last;
-    if (st[1] != 0.0) return;   // converged in an earlier launch (uniform)
-    const double lam = st[0];
-    double s = 0.0, k = 0.0;
-    for (size_t i = (size_t)blockIdx.x * PJ_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * PJ_NT) {
-        const float v = (float)((double)x[i] + c * (double)h[i]);
-        const double a = fabs((double)v);
-        if (a > lam) { s += a - lam; k += 1.0; }
+    if (st->done != 0.0) return;   // decided in an earlier pass (uniform)
+    const unsigned prefix = PASS == 1 ? 0u : st->prefix;
+    for (int b = threadIdx.x; b < NB; b += PJ_NT) lh[b] = 0ull;
+    if (threadIdx.x == 0) lbad = 0u;
+    __syncthreads();
+
+    unsigned bad = 0, cur = ~0u;
+    unsigned long long acc = 0ull;   // run of equal digits, added to LDS in one atomic
+    const size_t n4 = n / 4, stride = (size_t)gridDim.x * PJ_NT;
+    for (size_t j0 = (size_t)blockIdx.x * PJ_NT + threadIdx.x; j0 < n4; j0 += stride * SV_U) {
+        float4 xv[SV_U], hv[SV_U];
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+            xv[u] = ld4(x, j0 + u * stride, n4);   // zero padding: u = 0 is skipped
+            hv[u] = ld4(h, j0 + u * stride, n4);
+        }
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const unsigned m = __float_as_uint(pj_v(comp(xv[u], e), comp(hv[u], e), c)) & 0x7fffffffu;
+                if (m >= 0x7f800000u) { bad += PASS == 1; continue; }
+                if (m == 0u || (PASS > 1 && (m >> PSHIFT) != prefix)) continue;
+                const unsigned d = (m >> SHIFT) & (NB - 1);
+                if (d != cur) {
+                    if (acc) atomicAdd(&lh[cur], acc);
+                    cur = d;
+                    acc = 0ull;
+                }
+                acc += (1ull << CSHIFT) + (m & LOW);
+            }
+        }
     }
-    double t = block_reduce<false>(s, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-    t = block_reduce<false>(k, sh);
-    if (threadIdx.x == 0) {
-        part[gridDim.x + blockIdx.x] = t;
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    if (acc) atomicAdd(&lh[cur], acc);
+    if (PASS == 1 && bad) atomicAdd(&lbad, bad);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        // wave 0 adds the block's non-empty bins to the global histogram, then
+        // (lane 0) fences and takes the ticket: its own atomics are ordered
+        // before the ticket by the fence
+        for (int b = threadIdx.x; b < NB; b += 64) {
+            const unsigned long long v = lh[b];
+            if (v) {
+                atomicAdd(&hcnt[b], (unsigned)(v >> CSHIFT));
+                atomicAdd(&hsum[b], v & ((1ull << CSHIFT) - 1));
+            }
+        }
+        if (PASS == 1 && threadIdx.x == 0 && lbad) atomicAdd(hbad, lbad);
+        if (threadIdx.x == 0) {
+            __threadfence();
+            last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+        }
     }
     __syncthreads();
     if (!last) return;
     __threadfence();
-    double vs = 0.0, vk = 0.0;
-    for (int j = threadIdx.x; j < (int)gridDim.x; j += PJ_NT) {
-        vs += part[j];
-        vk += part[gridDim.x + j];
+
+    // ---- last block: read and clear the histogram, locate the root
+    __shared__ double sC[PJ_NT / 64], sV[PJ_NT / 64];
+    __shared__ int sb[PJ_NT / 64];
+    __shared__ double dC, dV, dS;   // the chosen bin's totals above it, S at its upper edge
+    constexpr int R = (NB + PJ_NT - 1) / PJ_NT;   // bins per thread
+    const int b0 = threadIdx.x * R;
+    double Cb[R], Vb[R];
+    double tC = 0.0, tV = 0.0;
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {   // high bins first, the order of the running sums below
+        const int b = b0 + r;
+        Cb[r] = 0.0;
+        Vb[r] = 0.0;
+        if (b < NB) {
+            const unsigned cnt = hcnt[b];
+            const unsigned long long low = hsum[b];
+            hcnt[b] = 0u;
+            hsum[b] = 0ull;
+            if (cnt) {
+                const unsigned ub = PASS == 1 ? (unsigned)b << 19
+                                  : PASS == 2 ? (prefix << 19) | ((unsigned)b << 7)
+                                              : (prefix << 7) | (unsigned)b;
+                const unsigned eb = ub >> 23;
+                const unsigned sig = (eb ? 0x800000u : 0u) | (ub & 0x7fffffu);   // significand of the bin's base
+                Cb[r] = (double)cnt;
+                Vb[r] = ldexp((double)cnt * (double)sig + (double)low, (int)(eb ? eb : 1u) - 150);
+            }
+        }
+        tC += Cb[r];
+        tV += Vb[r];
     }
-    const double S = block_reduce<false>(vs, sh);
-    const double K = block_reduce<false>(vk, sh);
+    // exclusive suffix sums of the thread totals over higher threads, in a fixed order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double iC = tC, iV = tV;   // inclusive suffix within the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double oC = __shfl_down(iC, off), oV = __shfl_down(iV, off);
+        if (lane + off < 64) { iC += oC; iV += oV; }
+    }
+    if (lane == 0) { sC[wave] = iC; sV[wave] = iV; }
+    double xC = __shfl_down(iC, 1), xV = __shfl_down(iV, 1);
+    if (lane == 63) { xC = 0.0; xV = 0.0; }
+    __syncthreads();
+    const double baseC = PASS == 1 ? 0.0 : st->C, baseV = PASS == 1 ? 0.0 : st->A;
+    double aC = baseC, aV = baseV;   // everything above this thread's bins
+    for (int w = PJ_NT / 64 - 1; w > wave; --w) { aC += sC[w]; aV += sV[w]; }
+    aC += xC;
+    aV += xV;
+    // this thread's highest bin whose lower edge has S >= tau
+    int cand = -1;
+    double cC = 0.0, cV = 0.0, cS = 0.0;
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {
+        const int b = b0 + r;
+        if (cand < 0 && b < NB && Cb[r] > 0.0) {
+            const unsigned ub = PASS == 1 ? (unsigned)b << 19
+                              : PASS == 2 ? (prefix << 19) | ((unsigned)b << 7)
+                                          : (prefix << 7) | (unsigned)b;
+            const unsigned uh = PASS == 1 ? (unsigned)(b + 1) << 19
+                              : PASS == 2 ? (prefix << 19) + ((unsigned)(b + 1) << 7)
+                                          : (prefix << 7) + (unsigned)(b + 1);
+            const double lo = (double)__uint_as_float(ub), hi = (double)__uint_as_float(uh);
+            const double Sge = (aV + Vb[r]) - (aC + Cb[r]) * lo;   // S at the bin's lower edge
+            if (Sge >= tau) {
+                cand = b;
+                cC = aC;
+                cV = aV;
+                cS = aV - aC * hi;   // S at its upper edge
+            }
+        }
+        aC += Cb[r];
+        aV += Vb[r];
+    }
+    int bm = cand;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) bm = max(bm, __shfl_xor(bm, off));
+    if (lane == 0) sb[wave] = bm;
+    __syncthreads();
+    int bstar = sb[0];
+    for (int w = 1; w < PJ_NT / 64; ++w) bstar = max(bstar, sb[w]);
+    if (bstar >= 0 && cand == bstar) {
+        dC = cC;
+        dV = cV;
+        dS = cS;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         *ticket = 0u;
-        if (fabs(S - tau) <= 1e-12 * tau || (lam == 0.0 && S <= tau)) st[1] = 1.0;
-        else st[0] = K > 0.0 ? fmax(0.0, lam + (S - tau) / K) : 0.0;   // K = 0: above every |v|
+        double lam = 0.0;
+        bool done = true;
+        const unsigned nbad = PASS == 1 ? *hbad : 0u;
+        if (PASS == 1) *hbad = 0u;
+        if (nbad) {
+            lam = __builtin_nan("");
+        } else if (bstar < 0) {
+            // the root lies below every element in play: all of them are active
+            // (aC, aV of thread 0 hold everything)
+            lam = aC > 0.0 ? fmax(0.0, (aV - tau) / aC) : 0.0;
+        } else if (dS >= tau || PASS == 3) {
+            // the root lies above the chosen bin's elements, where the active set
+            // is everything above the bin
+            if (dC > 0.0) {
+                lam = (dV - tau) / dC;
+            } else {   // nothing above: tau = 0 and every element goes to zero
+                const unsigned uh = PASS == 1 ? (unsigned)(bstar + 1) << 19
+                                  : PASS == 2 ? (prefix << 19) + ((unsigned)(bstar + 1) << 7)
+                                              : (prefix << 7) + (unsigned)(bstar + 1);
+                lam = (double)__uint_as_float(uh);
+            }
+        } else {
+            done = false;   // the root is inside bin bstar: the next pass refines it
+            st->prefix = PASS == 1 ? (unsigned)bstar : (prefix << 12) | (unsigned)bstar;
+            st->A = dV;
+            st->C = dC;
+        }
+        if (done) {
+            st->lam = lam;
+            st->done = 1.0;
+        }
     }
 }
 
-// xn = soft(x + c h, st[0]); partials: slot 0 sum -h.(xn - x), slot 1 sum |xn|,
-// slot 2 the done flag (so the host sees whether the steps converged).
+// xn = soft(x + c h, lam); partials: slot 0 sum -h.(xn - x), slot 1 sum |xn|,
+// slot 2 the done flag of the threshold (so the host can check it), which
+// block 0 then clears.
 __global__ __launch_bounds__(SV_NT) void k_sv_soft(const float* __restrict__ x, const float* __restrict__ h,
-                                                  double c, const double* __restrict__ st, size_t n,
+                                                  double c, PjState* __restrict__ st, size_t n,
                                                   float* __restrict__ xn, double* __restrict__ part) {
     __shared__ double sh[SV_NT / 64];
-    const double L = st[0];
+    const double L = st->lam;
     double s0 = 0.0, s1 = 0.0;
-    for (size_t i = (size_t)blockIdx.x * SV_NT + threadIdx.x; i < n; i += (size_t)gridDim.x * SV_NT) {
-        const float v = (float)((double)x[i] + c * (double)h[i]);
-        const double a = fabs((double)v) - L;
-        const float o = a > 0 ? (float)copysign(a, (double)v) : 0.0f;
-        xn[i] = o;
-        s0 += -(double)h[i] * ((double)o - (double)x[i]);
-        s1 += fabs((double)o);
+    const size_t n4 = n / 4, stride = (size_t)gridDim.x * SV_NT;
+    for (size_t j0 = (size_t)blockIdx.x * SV_NT + threadIdx.x; j0 < n4; j0 += stride * SV_U) {
+        float4 xv[SV_U], hv[SV_U];
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+            xv[u] = ld4(x, j0 + u * stride, n4);
+            hv[u] = ld4(h, j0 + u * stride, n4);
+        }
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+            float o4[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double xe = (double)comp(xv[u], e), he = (double)comp(hv[u], e);
+                const float v = pj_v(comp(xv[u], e), comp(hv[u], e), c);
+                const double a = fabs((double)v) - L;
+                // a NaN (from v or from lam) stays NaN
+                const float o = a > 0 ? (float)copysign(a, (double)v) : a <= 0 ? 0.0f : __builtin_nanf("");
+                o4[e] = o;
+                s0 += -he * ((double)o - xe);
+                s1 += fabs((double)o);
+            }
+            const size_t j = j0 + u * stride;
+            if (j < n4) reinterpret_cast<float4*>(xn)[j] = make_float4(o4[0], o4[1], o4[2], o4[3]);
+        }
     }
     double t = block_reduce<false>(s0, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
     t = block_reduce<false>(s1, sh);
     if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = t;
-    if (threadIdx.x == 0) part[2 * gridDim.x + blockIdx.x] = blockIdx.x == 0 ? st[1] : 0.0;
+    if (threadIdx.x == 0) {
+        part[2 * gridDim.x + blockIdx.x] = blockIdx.x == 0 ? st->done : 0.0;
+        if (blockIdx.x == 0) st->done = 0.0;   // the next projection starts at the first pass
+    }
 }
 
-// st[1] = 0 (a new projection; st[0] keeps the previous root as the start)
-__global__ void k_sv_pj_reset(double* __restrict__ st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st[1] = 0.0;
-}
-
-__global__ void k_sv_zero(double* __restrict__ p, unsigned* __restrict__ ticket) {
+__global__ void k_sv_zero(PjState* __restrict__ p, unsigned* __restrict__ ticket) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        p[0] = 0.0;
-        p[1] = 0.0;
+        *p = PjState{0.0, 0.0, 0.0, 0.0, 0u, 0u};
         *ticket = 0u;
     }
 }
@@ -299,8 +567,11 @@ struct SolveWork {
     std::vector<void*> allocs;
     float *x = nullptr, *xn = nullptr, *h = nullptr, *hn = nullptr;
     float *z = nullptr, *r = nullptr, *rn = nullptr, *bt = nullptr;
-    double *m = nullptr, *ring = nullptr, *Q = nullptr, *part = nullptr, *fin = nullptr, *lam = nullptr;
-    double* pj = nullptr;          // projection step partials, 2 x PJ_BLOCKS
+    double *m = nullptr, *ring = nullptr, *Q = nullptr, *part = nullptr, *fin = nullptr;
+    rn::PjState* pst = nullptr;     // projection threshold state
+    unsigned* hcnt = nullptr;       // projection histogram: counts, PJ_BINS
+    unsigned long long* hsum = nullptr;   // and significand sums below the digit, PJ_BINS
+    unsigned* hbad = nullptr;       // count of non-finite v
     unsigned* ticket = nullptr;    // last-block ticket of the projection steps
     ~SolveWork() {
         for (void* p : allocs) (void)hipFree(p);
@@ -323,6 +594,8 @@ std::vector<double> cubic_basis(int N) { return rn::ring_cubic_basis(N); }
 // fin slots: 0-1 residual (sum r^2, sum r.b~), 2-4 projection (g.dx, ||xn||_1,
 // converged flag), 5-8 spectral step (sum s^2, sum s.y, max |hn|, ||xn||_1)
 constexpr int FIN_RES = 0, FIN_PROJ = 2, FIN_BB = 5, FIN_COUNT = 9;
+constexpr unsigned FIN_MAX_OPS = (1u << (FIN_PROJ + 2)) | (1u << (FIN_BB + 2));   // the max slots
+static_assert(FIN_COUNT <= rn::SV_FIN_SLOTS, "fin slots");
 
 struct Solver {
     radon_plan_t plan;
@@ -337,14 +610,14 @@ struct Solver {
 
     void chk(hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; }
 
-    // fold SV_BLOCKS partials of `slots` slots into fin[off..off+slots) (no host wait)
-    void fold(int slots, unsigned ops, int off) {
-        hipLaunchKernelGGL(rn::k_sv_final, dim3(1), dim3(rn::SV_NT), 0, st, w.part, rn::SV_BLOCKS, slots, ops,
-                           w.fin + off);
-        chk(hipGetLastError());
-    }
-    // read all fin slots back (one host wait)
+    double* part(int slot) { return w.part + (size_t)slot * rn::SV_BLOCKS; }
+    // fold the per-block partials of every slot into fin and read fin back
+    // (one launch, one host wait; slots no kernel wrote since the last read
+    // hold their earlier partials)
     bool read(double* out) {
+        hipLaunchKernelGGL(rn::k_sv_final, dim3(1), dim3(rn::SV_NT), 0, st, w.part, rn::SV_BLOCKS, FIN_COUNT,
+                           FIN_MAX_OPS, w.fin);
+        chk(hipGetLastError());
         chk(hipMemcpyAsync(out, w.fin, sizeof(double) * FIN_COUNT, hipMemcpyDeviceToHost, st));
         chk(hipStreamSynchronize(st));
         return err == hipSuccess;
@@ -360,42 +633,40 @@ struct Solver {
             ring = w.ring;
         }
         hipLaunchKernelGGL(rn::k_sv_resid, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, b, z, ring, bt, p.n_views,
-                           p.n_det, r, w.part);
+                           p.n_det, r, part(FIN_RES));
         chk(hipGetLastError());
-        fold(2, 0u, FIN_RES);
     }
 
     // xn = P_tau(x + c h) -> fin[2] = sum -h.(xn - x), fin[3] = ||xn||_1,
-    // fin[4] = 1 if the Newton steps converged (else call again with fresh = false
-    // to continue them)
-    void project(const float* x, const float* h, double c, double tau, float* xn, bool fresh = true) {
-        if (fresh) hipLaunchKernelGGL(rn::k_sv_pj_reset, dim3(1), dim3(64), 0, st, w.lam);
-        for (int k = 0; k < rn::PJ_STEPS; ++k)
-            hipLaunchKernelGGL(rn::k_sv_pj_step, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, n2, w.lam,
-                               w.pj, w.ticket);
-        hipLaunchKernelGGL(rn::k_sv_soft, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, h, c, w.lam, n2, xn,
-                           w.part);
+    // fin[4] = 1 (the threshold is final after the three passes)
+    void project(const float* x, const float* h, double c, double tau, float* xn) {
+        hipLaunchKernelGGL(rn::k_sv_pj_pass<1>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, n2, w.pst,
+                           w.hcnt, w.hsum, w.hbad, w.ticket);
+        hipLaunchKernelGGL(rn::k_sv_pj_pass<2>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, n2, w.pst,
+                           w.hcnt, w.hsum, w.hbad, w.ticket);
+        hipLaunchKernelGGL(rn::k_sv_pj_pass<3>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, n2, w.pst,
+                           w.hcnt, w.hsum, w.hbad, w.ticket);
+        hipLaunchKernelGGL(rn::k_sv_soft, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, h, c, w.pst, n2, xn,
+                           part(FIN_PROJ));
         chk(hipGetLastError());
-        fold(3, 1u << 2, FIN_PROJ);
     }
 
     // spectral-step sums of s = xn - x, y = -(hn - h) -> fin[4..7] (x, h may be null)
     void bb(const float* x, const float* xn, const float* h, const float* hn) {
-        hipLaunchKernelGGL(rn::k_sv_bb, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, xn, h, hn, n2, w.part);
+        hipLaunchKernelGGL(rn::k_sv_bb, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, xn, h, hn, n2, part(FIN_BB));
         chk(hipGetLastError());
-        fold(4, 1u << 2, FIN_BB);
     }
 
-    // project and wait until the Newton steps have converged
+    // project and read fin back; fin[4] != 1 would be an internal error
     bool project_sync(const float* x, const float* h, double c, double tau, float* xn, double* fin) {
-        bool fresh = true;
-        for (int round = 0; round < 64; ++round) {
-            project(x, h, c, tau, xn, fresh);
-            fresh = false;
-            if (!read(fin)) return false;
-            if (fin[FIN_PROJ + 2] != 0.0) return true;
-        }
-        return true;   // the last step's threshold is used
+        project(x, h, c, tau, xn);
+        return read(fin) && projected(fin);
+    }
+    bool projected(const double* fin) {
+        if (fin[FIN_PROJ + 2] == 1.0) return true;
+        err = hipErrorUnknown;
+        rn::api_fail(RADON_ERR_DEVICE, "radon_solve_bpdn: the l1 projection did not finish");
+        return false;
     }
 
     bool forward(const float* x, float* z) {
@@ -533,7 +804,7 @@ radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, 
     double fin[FIN_COUNT];
     out = RunOut{};
     // projection state: threshold 0 (no warm start yet), ticket 0
-    hipLaunchKernelGGL(rn::k_sv_zero, dim3(1), dim3(64), 0, st, w.lam, w.ticket);
+    hipLaunchKernelGGL(rn::k_sv_zero, dim3(1), dim3(64), 0, st, w.pst, w.ticket);
     // start point, tau = ||x0||_1, and the projection of x0 (a no-op at that radius)
     if (!warm) hipLaunchKernelGGL(rn::k_sv_fill, dim3(1024), dim3(256), 0, st, w.x, S.n2, 0.0f);
     S.bb(nullptr, w.x, nullptr, w.x);
@@ -604,17 +875,12 @@ radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, 
         const double fmax = *std::max_element(fs.begin(), fs.end());
         double step = 1.0, fn = 0, rbtn = 0;
         while (true) {
-            bool fresh = true;
-            for (int round = 0; round < 64; ++round) {   // rarely more than one round
-                S.project(w.x, w.h, step * alpha, tau, w.xn, fresh);
-                fresh = false;
-                if (!S.forward(w.xn, w.z)) return RADON_ERR_DEVICE;
-                S.residual(w.z, w.rn, w.bt);
-                if (!S.adjoint(w.rn, w.hn)) return RADON_ERR_DEVICE;
-                S.bb(w.x, w.xn, w.h, w.hn);
-                if (!S.read(fin)) return RADON_ERR_DEVICE;
-                if (fin[FIN_PROJ + 2] != 0.0) break;
-            }
+            S.project(w.x, w.h, step * alpha, tau, w.xn);
+            if (!S.forward(w.xn, w.z)) return RADON_ERR_DEVICE;
+            S.residual(w.z, w.rn, w.bt);
+            if (!S.adjoint(w.rn, w.hn)) return RADON_ERR_DEVICE;
+            S.bb(w.x, w.xn, w.h, w.hn);
+            if (!S.read(fin) || !S.projected(fin)) return RADON_ERR_DEVICE;
             const double gtd = fin[FIN_PROJ];
             fn = 0.5 * fin[FIN_RES];
             rbtn = fin[FIN_RES + 1];
@@ -660,13 +926,20 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
     if (!w.alloc(&w.x, n2) || !w.alloc(&w.xn, n2) || !w.alloc(&w.h, n2) || !w.alloc(&w.hn, n2) ||
         !w.alloc(&w.z, ns) || !w.alloc(&w.r, ns) || !w.alloc(&w.rn, ns) || !w.alloc(&w.bt, ns) ||
         !w.alloc(&w.m, p.n_det) || !w.alloc(&w.ring, p.n_det) || !w.alloc(&w.Q, (size_t)p.n_det * 4) ||
-        !w.alloc(&w.part, (size_t)rn::SV_SLOTS * rn::SV_BLOCKS) || !w.alloc(&w.fin, FIN_COUNT) ||
-        !w.alloc(&w.lam, 2) || !w.alloc(&w.pj, (size_t)2 * rn::PJ_BLOCKS) || !w.alloc(&w.ticket, 1))
+        !w.alloc(&w.part, (size_t)FIN_COUNT * rn::SV_BLOCKS) || !w.alloc(&w.fin, FIN_COUNT) ||
+        !w.alloc(&w.pst, 1) || !w.alloc(&w.hcnt, rn::PJ_BINS) || !w.alloc(&w.hsum, rn::PJ_BINS) ||
+        !w.alloc(&w.hbad, 1) || !w.alloc(&w.ticket, 1))
         return RADON_ERR_OOM;
     hipStream_t st = (hipStream_t)stream;
     Solver S{plan, p, w, st, opts->ring_filter != 0, b_dev, n2, ns};
     const std::vector<double> Q = cubic_basis(p.n_det);
     S.chk(hipMemcpyAsync(w.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice, st));
+    // every read folds all partial slots, also those no kernel has written yet;
+    // the projection passes leave their histogram cleared, so it starts cleared
+    S.chk(hipMemsetAsync(w.part, 0, sizeof(double) * FIN_COUNT * rn::SV_BLOCKS, st));
+    S.chk(hipMemsetAsync(w.hcnt, 0, sizeof(unsigned) * rn::PJ_BINS, st));
+    S.chk(hipMemsetAsync(w.hsum, 0, sizeof(unsigned long long) * rn::PJ_BINS, st));
+    S.chk(hipMemsetAsync(w.hbad, 0, sizeof(unsigned), st));
 
     double fin[FIN_COUNT];
     // b~ = F b and its norm
