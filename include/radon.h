@@ -338,6 +338,26 @@ radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev, float* x_
                                 radon_solve_stats* stats, void* stream);
 
 /*
+ * Euclidean projection onto the l1 ball {||x||_1 <= tau}, the projection of
+ * the solver's projected-gradient steps (SPGL1, introduction):
+ * out = sign(v) max(|v| - lam, 0) with lam >= 0 the exact root of
+ * sum max(|v_i| - lam, 0) = tau (lam = 0 when sum |v_i| <= tau; lam at or
+ * above max |v_i| when tau = 0), located by a deterministic three-level
+ * radix select on the bit patterns of |v_i|, so the result does not depend
+ * on the launch order and lam is exact up to the final float64 sums.
+ * v_dev, out_dev: n float32 values on the device (may alias), 16-byte
+ * aligned, n a multiple of 4 (the solver's images are). A NaN or infinite
+ * v_i gives lam = NaN and NaN outputs. lam_host (may be NULL) receives lam.
+ * The call allocates its workspace, runs on `stream` and synchronises it.
+ * Errors: RADON_ERR_INVALID for NULL buffers with n > 0, n < 0, n not a
+ * multiple of 4, misaligned buffers, or tau negative or not finite;
+ * RADON_ERR_UNSUPPORTED for n > 2^29; RADON_ERR_OOM when the workspace
+ * cannot be allocated; RADON_ERR_DEVICE for launch failures.
+ */
+radon_status_t radon_project_l1(const float* v_dev, int64_t n, double tau, float* out_dev, double* lam_host,
+                                void* stream);
+
+/*
  * Learned warm start (an extension beyond the paper, which starts its solves
  * from zero): a 4-level convolutional encoder-decoder (3x3 convolutions,
  * 32-64-128-256 channels, ReLU, 2x2 average pooling, nearest upsampling, skip

@@ -60,31 +60,33 @@ __device__ double block_reduce(double v, double* sh) {
     return r;   // valid in thread 0
 }
 
-// Sum (or max) of the per-block partials of each slot, in block order:
-// every thread folds its strided share of each slot, the waves reduce
-// them, and thread s adds the wave results of slot s in wave order.
-// ops bit k set: slot k is a max, else a sum. nslots <= SV_FIN_SLOTS.
+// Sum (or max) of the SV_BLOCKS per-block partials of each slot, in block
+// order: every thread loads its strided share of every slot at once, folds it,
+// the waves reduce, and thread s adds the wave results of slot s in wave order.
+// ops bit k set: slot k is a max, else a sum. nslots <= SV_FIN_SLOTS. out may
+// be pinned host memory, which the host reads once the stream has finished.
 constexpr int SV_FIN_SLOTS = 9;
-__global__ __launch_bounds__(SV_NT) void k_sv_final(const double* __restrict__ part, int nb, int nslots,
-                                                   unsigned ops, double* __restrict__ out) {
+__global__ __launch_bounds__(SV_NT) void k_sv_final(const double* __restrict__ part, int nslots, unsigned ops,
+                                                   double* __restrict__ out) {
+    constexpr int PER = (SV_BLOCKS + SV_NT - 1) / SV_NT;
     __shared__ double sh[SV_FIN_SLOTS][SV_NT / 64];
-    double v[SV_FIN_SLOTS];
+    double p[SV_FIN_SLOTS][PER];
 #pragma unroll
-    for (int s = 0; s < SV_FIN_SLOTS; ++s) v[s] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += SV_NT) {
+    for (int s = 0; s < SV_FIN_SLOTS; ++s)
 #pragma unroll
-        for (int s = 0; s < SV_FIN_SLOTS; ++s) {
-            if (s < nslots) {
-                const double p = part[(size_t)s * nb + b];
-                v[s] = ((ops >> s) & 1u) ? fmax(v[s], p) : v[s] + p;
-            }
+        for (int k = 0; k < PER; ++k) {
+            const int b = threadIdx.x + k * SV_NT;
+            p[s][k] = (s < nslots && b < SV_BLOCKS) ? part[(size_t)s * SV_BLOCKS + b] : 0.0;
         }
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int s = 0; s < SV_FIN_SLOTS; ++s) {
-        const double r = ((ops >> s) & 1u) ? wave_max(v[s]) : wave_sum(v[s]);
-        if (lane == 0) sh[s][wave] = r;
+        const bool mx = (ops >> s) & 1u;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) v = mx ? fmax(v, p[s][k]) : v + p[s][k];
+        v = mx ? wave_max(v) : wave_sum(v);
+        if (lane == 0) sh[s][wave] = v;
     }
     __syncthreads();
     const int s = threadIdx.x;
@@ -97,29 +99,18 @@ __global__ __launch_bounds__(SV_NT) void k_sv_final(const double* __restrict__ p
 }
 
 // m[d] = mean over views of (b - z)[., d] (z may be null: m = mean of b).
-// A block takes 32 detectors; its 8 thread groups sum every 8th view (the
-// loads of 8 views issued before they are added, in view order), and the 8
-// group sums are added in group order.
+// A block takes 32 detectors; its 8 thread groups sum every 8th view, and the
+// 8 group sums are added in group order.
 __global__ __launch_bounds__(256) void k_sv_colmean(const float* __restrict__ b, const float* __restrict__ z,
                                                    int nv, int N, double* __restrict__ m) {
-    constexpr int U = 8;
     __shared__ double part[8][32];
     const int dl = threadIdx.x & 31, g = threadIdx.x >> 5;
     const int d = blockIdx.x * 32 + dl;
     double s = 0.0;
     if (d < N) {
-        for (int a0 = g; a0 < nv; a0 += 8 * U) {
-            float bv[U], zv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int a = a0 + 8 * u;
-                const size_t i = (size_t)a * N + d;
-                bv[u] = a < nv ? b[i] : 0.0f;
-                zv[u] = (z && a < nv) ? z[i] : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (a0 + 8 * u < nv) s += (double)bv[u] - (z ? (double)zv[u] : 0.0);
+        for (int a = g; a < nv; a += 8) {
+            const size_t i = (size_t)a * N + d;
+            s += (double)b[i] - (z ? (double)z[i] : 0.0);
         }
     }
     part[g][dl] = s;
@@ -248,144 +239,114 @@ __global__ __launch_bounds__(SV_NT) void k_sv_bb(const float* __restrict__ x, co
 // piecewise linear with breakpoints at the values |v_i|, so the root is found
 // exactly by locating it between two consecutive values: a radix select on the
 // bit pattern u of |v| (monotone in |v| for non-negative floats), 12 + 12 + 7
-// bits in three passes. Each pass histograms the elements whose leading bits
+// bits in three levels. Each level histograms the elements whose leading bits
 // match the bin chosen so far, by count and by the exact integer sum of their
-// significands (the bins of a pass share one exponent), so the histograms are
+// significands (the bins of a level share one exponent), so the histograms are
 // order-independent integers and the select is deterministic. From the counts
-// and sums above each bin edge e the last block evaluates S(e) exactly up to
-// the final float64 sums, takes the highest non-empty bin whose lower edge
-// has S >= tau, and either finishes (the root lies in an empty gap, below every
-// element in play, or the bins are single values) with
-// lam = (sum of |v| above the root - tau) / (their count), or descends into
-// that bin. Special cases: sum |v| <= tau gives lam = 0 (v is in the ball);
-// tau = 0 gives a lam at or above max |v|; a NaN or infinite v gives lam = NaN,
-// which the soft threshold turns into NaN outputs.
-// One launch per pass: every block histograms its elements in LDS, one wave
-// adds the non-empty bins to the global histogram with integer atomics and
-// takes the block's ticket after a memory fence, and the last block to finish
-// reads and clears the global histogram and decides. Passes after the
-// decision return at once.
+// and sums above each bin edge e, S(e) is exact up to the final float64 sums;
+// the highest non-empty bin whose lower edge has S >= tau is either refined by
+// the next level or, when the root lies in an empty gap, below every element
+// in play, or the bins are single values, gives
+// lam = (sum of |v| above the root - tau) / (their count). Special cases:
+// sum |v| <= tau gives lam = 0 (v is in the ball); tau = 0 gives a lam at or
+// above max |v|; a NaN or infinite v gives lam = NaN, which the soft threshold
+// turns into NaN outputs.
+// Launches: the level-1, level-2 and level-3 histogram passes, then the soft
+// threshold. There is no grid-wide wait inside a launch: every block of the
+// next launch takes the previous level's decision itself from the finished
+// histogram (the same decision in every block), so the kernel boundary is the
+// only synchronisation, and block 0 records it for the launches after.
 constexpr int PJ_NT = 256;
 #ifndef RN_PJ_BLOCKS
 #define RN_PJ_BLOCKS 256
 #endif
 constexpr int PJ_BLOCKS = RN_PJ_BLOCKS;
-constexpr int PJ_BINS = 4096;   // bins of the first two passes (12 bits each); the third has 128
-constexpr int PJ_PASSES = 3;
+constexpr int PJ_BINS = 4096;    // bins of levels 1 and 2 (12 bits each)
+constexpr int PJ_BINS3 = 128;    // bins of level 3 (7 bits: one float value each)
 
+// Decision after a level: the threshold (done), or the bin to refine (the
+// leading bits of u fixed so far) with the sum and count of |v| above it.
 struct PjState {
-    double lam;        // the threshold, final once done != 0
-    double done;       // 1 once lam is final
-    double A, C;       // sum and count of |v| above the bin chosen so far
-    unsigned prefix;   // leading bits of u fixed by the passes so far
-    unsigned pad;
+    double lam, done, A, C;
+    unsigned prefix, pad;
+};
+
+// Global histograms of the three levels (counts; sums of the bits below the
+// digit), the count of non-finite v, and the decisions after levels 1 and 2.
+// A level's histogram is cleared by a launch after the one that reads it.
+struct PjWork {
+    unsigned *cnt1, *cnt2, *cnt3;
+    unsigned long long *sum1, *sum2, *sum3;
+    unsigned* bad;
+    PjState *st1, *st2;
+};
+
+template <int L>
+struct PjLevel {
+    static constexpr int NB = L == 3 ? PJ_BINS3 : PJ_BINS;
+    static constexpr int SHIFT = L == 1 ? 19 : L == 2 ? 7 : 0;   // digit = (u >> SHIFT) % NB
+    static constexpr int PSHIFT = SHIFT + (L == 3 ? 7 : 12);      // u >> PSHIFT must equal the prefix
+    // bit pattern of the lower edge of bin b (b = NB carries into the prefix)
+    __device__ static unsigned edge(unsigned prefix, unsigned b) {
+        return L == 1 ? b << 19 : L == 2 ? (prefix << 19) + (b << 7) : (prefix << 7) + b;
+    }
 };
 
 // v exactly as the soft threshold forms it
 __device__ __forceinline__ float pj_v(float x, float h, double c) { return (float)((double)x + c * (double)h); }
 
-template <int PASS>
-__global__ __launch_bounds__(PJ_NT) void k_sv_pj_pass(const float* __restrict__ x, const float* __restrict__ h,
-                                                     double c, double tau, size_t n, PjState* __restrict__ st,
-                                                     unsigned* __restrict__ hcnt, unsigned long long* __restrict__ hsum,
-                                                     unsigned* __restrict__ hbad, unsigned* __restrict__ ticket) {
-    constexpr int NB = PASS == 3 ? 128 : PJ_BINS;
-    constexpr int SHIFT = PASS == 1 ? 19 : PASS == 2 ? 7 : 0;   // digit = (u >> SHIFT) % NB
-    constexpr int PSHIFT = SHIFT + (PASS == 3 ? 7 : 12);          // u >> PSHIFT must equal the prefix
-    constexpr unsigned LOW = (1u << SHIFT) - 1;                    // bits below the digit
-    constexpr int CSHIFT = 40;   // LDS bin: count << 40 | sum of the bits below the digit
-    __shared__ unsigned long long lh[NB];
-    __shared__ unsigned lbad;
-    __shared__ bool last;
-    if (st->done != 0.0) return;   // decided in an earlier pass (uniform)
-    const unsigned prefix = PASS == 1 ? 0u : st->prefix;
-    for (int b = threadIdx.x; b < NB; b += PJ_NT) lh[b] = 0ull;
-    if (threadIdx.x == 0) lbad = 0u;
-    __syncthreads();
-
-    unsigned bad = 0, cur = ~0u;
-    unsigned long long acc = 0ull;   // run of equal digits, added to LDS in one atomic
-    const size_t n4 = n / 4, stride = (size_t)gridDim.x * PJ_NT;
-    for (size_t j0 = (size_t)blockIdx.x * PJ_NT + threadIdx.x; j0 < n4; j0 += stride * SV_U) {
-        float4 xv[SV_U], hv[SV_U];
-#pragma unroll
-        for (int u = 0; u < SV_U; ++u) {
-            xv[u] = ld4(x, j0 + u * stride, n4);   // zero padding: u = 0 is skipped
-            hv[u] = ld4(h, j0 + u * stride, n4);
-        }
-#pragma unroll
-        for (int u = 0; u < SV_U; ++u) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const unsigned m = __float_as_uint(pj_v(comp(xv[u], e), comp(hv[u], e), c)) & 0x7fffffffu;
-                if (m >= 0x7f800000u) { bad += PASS == 1; continue; }
-                if (m == 0u || (PASS > 1 && (m >> PSHIFT) != prefix)) continue;
-                const unsigned d = (m >> SHIFT) & (NB - 1);
-                if (d != cur) {
-                    if (acc) atomicAdd(&lh[cur], acc);
-                    cur = d;
-                    acc = 0ull;
-                }
-                acc += (1ull << CSHIFT) + (m & LOW);
-            }
-        }
-    }
-    if (acc) atomicAdd(&lh[cur], acc);
-    if (PASS == 1 && bad) atomicAdd(&lbad, bad);
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        // wave 0 adds the block's non-empty bins to the global histogram, then
-        // (lane 0) fences and takes the ticket: its own atomics are ordered
-        // before the ticket by the fence
-        for (int b = threadIdx.x; b < NB; b += 64) {
-            const unsigned long long v = lh[b];
-            if (v) {
-                atomicAdd(&hcnt[b], (unsigned)(v >> CSHIFT));
-                atomicAdd(&hsum[b], v & ((1ull << CSHIFT) - 1));
-            }
-        }
-        if (PASS == 1 && threadIdx.x == 0 && lbad) atomicAdd(hbad, lbad);
-        if (threadIdx.x == 0) {
-            __threadfence();
-            last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-        }
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-
-    // ---- last block: read and clear the histogram, locate the root
+// Block-wide: the decision of level L from its finished histogram, given the
+// decision above it (up: prefix, and the sum A and count C of |v| above the bin
+// it chose; zero for level 1). Every thread returns the same decision. lc, ls:
+// shared scratch of NB entries, free again when this returns.
+template <int L>
+__device__ PjState pj_decide(const unsigned* __restrict__ hcnt, const unsigned long long* __restrict__ hsum,
+                             unsigned nbad, const PjState& up, double tau, unsigned* lc, unsigned long long* ls) {
+    using Lv = PjLevel<L>;
+    constexpr int NB = Lv::NB;
+    constexpr int RL = (NB + PJ_NT - 1) / PJ_NT;
     __shared__ double sC[PJ_NT / 64], sV[PJ_NT / 64];
     __shared__ int sb[PJ_NT / 64];
-    __shared__ double dC, dV, dS;   // the chosen bin's totals above it, S at its upper edge
-    constexpr int R = (NB + PJ_NT - 1) / PJ_NT;   // bins per thread
-    const int b0 = threadIdx.x * R;
-    double Cb[R], Vb[R];
+    __shared__ double dC, dV, dS;   // the chosen bin: count and sum above it, S at its upper edge
+    __shared__ PjState out;
+    const unsigned prefix = L == 1 ? 0u : up.prefix;
+    {   // coalesced loads, all in flight at once, into LDS
+        unsigned cv[RL];
+        unsigned long long sv[RL];
+#pragma unroll
+        for (int k = 0; k < RL; ++k) {
+            const int b = threadIdx.x + k * PJ_NT;
+            cv[k] = b < NB ? hcnt[b] : 0u;
+            sv[k] = b < NB ? hsum[b] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < RL; ++k) {
+            const int b = threadIdx.x + k * PJ_NT;
+            if (b < NB) { lc[b] = cv[k]; ls[b] = sv[k]; }
+        }
+    }
+    __syncthreads();
+    // this thread's RL consecutive bins: count and exact value sum of each
+    const int b0 = threadIdx.x * RL;
+    double Cb[RL], Vb[RL];
     double tC = 0.0, tV = 0.0;
 #pragma unroll
-    for (int r = R - 1; r >= 0; --r) {   // high bins first, the order of the running sums below
+    for (int r = RL - 1; r >= 0; --r) {   // high bins first, the order of the running sums below
         const int b = b0 + r;
         Cb[r] = 0.0;
         Vb[r] = 0.0;
-        if (b < NB) {
-            const unsigned cnt = hcnt[b];
-            const unsigned long long low = hsum[b];
-            hcnt[b] = 0u;
-            hsum[b] = 0ull;
-            if (cnt) {
-                const unsigned ub = PASS == 1 ? (unsigned)b << 19
-                                  : PASS == 2 ? (prefix << 19) | ((unsigned)b << 7)
-                                              : (prefix << 7) | (unsigned)b;
-                const unsigned eb = ub >> 23;
-                const unsigned sig = (eb ? 0x800000u : 0u) | (ub & 0x7fffffu);   // significand of the bin's base
-                Cb[r] = (double)cnt;
-                Vb[r] = ldexp((double)cnt * (double)sig + (double)low, (int)(eb ? eb : 1u) - 150);
-            }
+        if (b < NB && lc[b]) {
+            const unsigned cnt = lc[b];
+            const unsigned ub = Lv::edge(prefix, (unsigned)b);
+            const unsigned eb = ub >> 23;
+            const unsigned sig = (eb ? 0x800000u : 0u) | (ub & 0x7fffffu);   // significand of the bin's edge
+            Cb[r] = (double)cnt;
+            Vb[r] = ldexp((double)cnt * (double)sig + (double)ls[b], (int)(eb ? eb : 1u) - 150);
         }
         tC += Cb[r];
         tV += Vb[r];
     }
-    // exclusive suffix sums of the thread totals over higher threads, in a fixed order
+    // exclusive suffix sums of the thread totals over the higher threads, in a fixed order
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double iC = tC, iV = tV;   // inclusive suffix within the wave
 #pragma unroll
@@ -397,31 +358,24 @@ __global__ __launch_bounds__(PJ_NT) void k_sv_pj_pass(const float* __restrict__ 
     double xC = __shfl_down(iC, 1), xV = __shfl_down(iV, 1);
     if (lane == 63) { xC = 0.0; xV = 0.0; }
     __syncthreads();
-    const double baseC = PASS == 1 ? 0.0 : st->C, baseV = PASS == 1 ? 0.0 : st->A;
-    double aC = baseC, aV = baseV;   // everything above this thread's bins
+    double aC = L == 1 ? 0.0 : up.C, aV = L == 1 ? 0.0 : up.A;   // everything above this thread's bins
     for (int w = PJ_NT / 64 - 1; w > wave; --w) { aC += sC[w]; aV += sV[w]; }
     aC += xC;
     aV += xV;
-    // this thread's highest bin whose lower edge has S >= tau
+    // this thread's highest non-empty bin whose lower edge has S >= tau
     int cand = -1;
     double cC = 0.0, cV = 0.0, cS = 0.0;
 #pragma unroll
-    for (int r = R - 1; r >= 0; --r) {
+    for (int r = RL - 1; r >= 0; --r) {
         const int b = b0 + r;
-        if (cand < 0 && b < NB && Cb[r] > 0.0) {
-            const unsigned ub = PASS == 1 ? (unsigned)b << 19
-                              : PASS == 2 ? (prefix << 19) | ((unsigned)b << 7)
-                                          : (prefix << 7) | (unsigned)b;
-            const unsigned uh = PASS == 1 ? (unsigned)(b + 1) << 19
-                              : PASS == 2 ? (prefix << 19) + ((unsigned)(b + 1) << 7)
-                                          : (prefix << 7) + (unsigned)(b + 1);
-            const double lo = (double)__uint_as_float(ub), hi = (double)__uint_as_float(uh);
-            const double Sge = (aV + Vb[r]) - (aC + Cb[r]) * lo;   // S at the bin's lower edge
-            if (Sge >= tau) {
+        if (cand < 0 && Cb[r] > 0.0) {
+            const double lo = (double)__uint_as_float(Lv::edge(prefix, (unsigned)b));
+            const double hi = (double)__uint_as_float(Lv::edge(prefix, (unsigned)b + 1u));
+            if ((aV + Vb[r]) - (aC + Cb[r]) * lo >= tau) {
                 cand = b;
                 cC = aC;
                 cV = aV;
-                cS = aV - aC * hi;   // S at its upper edge
+                cS = aV - aC * hi;
             }
         }
         aC += Cb[r];
@@ -441,50 +395,155 @@ __global__ __launch_bounds__(PJ_NT) void k_sv_pj_pass(const float* __restrict__ 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        *ticket = 0u;
-        double lam = 0.0;
-        bool done = true;
-        const unsigned nbad = PASS == 1 ? *hbad : 0u;
-        if (PASS == 1) *hbad = 0u;
+        PjState d{0.0, 1.0, 0.0, 0.0, 0u, 0u};
         if (nbad) {
-            lam = __builtin_nan("");
+            d.lam = __builtin_nan("");
         } else if (bstar < 0) {
             // the root lies below every element in play: all of them are active
             // (aC, aV of thread 0 hold everything)
-            lam = aC > 0.0 ? fmax(0.0, (aV - tau) / aC) : 0.0;
-        } else if (dS >= tau || PASS == 3) {
-            // the root lies above the chosen bin's elements, where the active set
-            // is everything above the bin
-            if (dC > 0.0) {
-                lam = (dV - tau) / dC;
-            } else {   // nothing above: tau = 0 and every element goes to zero
-                const unsigned uh = PASS == 1 ? (unsigned)(bstar + 1) << 19
-                                  : PASS == 2 ? (prefix << 19) + ((unsigned)(bstar + 1) << 7)
-                                              : (prefix << 7) + (unsigned)(bstar + 1);
-                lam = (double)__uint_as_float(uh);
-            }
-        } else {
-            done = false;   // the root is inside bin bstar: the next pass refines it
-            st->prefix = PASS == 1 ? (unsigned)bstar : (prefix << 12) | (unsigned)bstar;
-            st->A = dV;
-            st->C = dC;
+            d.lam = aC > 0.0 ? fmax(0.0, (aV - tau) / aC) : 0.0;
+        } else if (dS >= tau || L == 3) {
+            // the root lies above the chosen bin's elements: the active set is
+            // everything above the bin (nothing above: tau = 0, all go to zero)
+            d.lam = dC > 0.0 ? (dV - tau) / dC : (double)__uint_as_float(Lv::edge(prefix, (unsigned)bstar + 1u));
+        } else {   // the root is inside bin bstar: the next level refines it
+            d.done = 0.0;
+            d.A = dV;
+            d.C = dC;
+            d.prefix = L == 1 ? (unsigned)bstar : (prefix << 12) | (unsigned)bstar;
         }
-        if (done) {
-            st->lam = lam;
-            st->done = 1.0;
-        }
+        out = d;
     }
+    __syncthreads();
+    return out;
 }
 
-// xn = soft(x + c h, lam); partials: slot 0 sum -h.(xn - x), slot 1 sum |xn|,
-// slot 2 the done flag of the threshold (so the host can check it), which
-// block 0 then clears.
+// Level-L histogram pass. The step c and the radius tau are arguments of the
+// level-1 pass, whose block 0 copies them to ct for the later launches; the
+// level-2 and level-3 passes (c, tau unused) read them from ct. For L > 1
+// every block first takes the decision of level L - 1 (block 0 records it);
+// nothing is left to do once it is final.
+template <int L>
+__global__ __launch_bounds__(PJ_NT) void k_sv_pj_pass(const float* __restrict__ x, const float* __restrict__ h,
+                                                     double c, double tau, double* __restrict__ ct, size_t n,
+                                                     PjWork w) {
+    using Lv = PjLevel<L>;
+    constexpr int NB = Lv::NB;
+    constexpr unsigned LOW = (1u << Lv::SHIFT) - 1;   // bits below the digit
+    constexpr int CSHIFT = 40;   // LDS bin: count << 40 | sum of the bits below the digit
+    __shared__ unsigned long long lh[PJ_BINS];
+    __shared__ unsigned lc[PJ_BINS];
+    __shared__ unsigned lbad;
+    const size_t n4 = n / 4, stride = (size_t)gridDim.x * PJ_NT;
+    const size_t jfirst = (size_t)blockIdx.x * PJ_NT + threadIdx.x;
+    float4 xv[SV_U], hv[SV_U];   // the first round's pieces, in flight during the decision
+#pragma unroll
+    for (int u = 0; u < SV_U; ++u) {
+        xv[u] = ld4(x, jfirst + u * stride, n4);   // zero padding: u = 0 is skipped
+        hv[u] = ld4(h, jfirst + u * stride, n4);
+    }
+    if (L == 1) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) { ct[0] = c; ct[1] = tau; }
+    } else {
+        c = ct[0];
+        tau = ct[1];
+    }
+    unsigned prefix = 0u;
+    if (L == 1) {
+        // the level-3 histogram was read by the last soft threshold: clear it
+        if (blockIdx.x == 0 && threadIdx.x < PJ_BINS3) {
+            w.cnt3[threadIdx.x] = 0u;
+            w.sum3[threadIdx.x] = 0ull;
+        }
+    } else {
+        PjState up{0.0, 0.0, 0.0, 0.0, 0u, 0u};
+        if (L == 3) {
+            up = *w.st1;
+            if (up.done != 0.0) return;   // final after level 1 (uniform)
+        }
+        const PjState d = L == 2 ? pj_decide<1>(w.cnt1, w.sum1, *w.bad, up, tau, lc, lh)
+                                 : pj_decide<2>(w.cnt2, w.sum2, 0u, up, tau, lc, lh);
+        if (blockIdx.x == 0 && threadIdx.x == 0) *(L == 2 ? w.st1 : w.st2) = d;
+        if (d.done != 0.0) return;   // uniform
+        prefix = d.prefix;
+    }
+    for (int b = threadIdx.x; b < NB; b += PJ_NT) lh[b] = 0ull;
+    if (threadIdx.x == 0) lbad = 0u;
+    __syncthreads();
+
+    unsigned bad = 0, cur = ~0u;
+    unsigned long long acc = 0ull;   // run of equal digits, added to LDS in one atomic
+    for (size_t j0 = jfirst; j0 < n4; j0 += stride * SV_U) {
+        if (j0 != jfirst) {
+#pragma unroll
+            for (int u = 0; u < SV_U; ++u) {
+                xv[u] = ld4(x, j0 + u * stride, n4);
+                hv[u] = ld4(h, j0 + u * stride, n4);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const unsigned m = __float_as_uint(pj_v(comp(xv[u], e), comp(hv[u], e), c)) & 0x7fffffffu;
+                if (m >= 0x7f800000u) { bad += L == 1; continue; }
+                if (m == 0u || (L > 1 && (m >> Lv::PSHIFT) != prefix)) continue;
+                const unsigned dg = (m >> Lv::SHIFT) & (NB - 1);
+                if (dg != cur) {
+                    if (acc) atomicAdd(&lh[cur], acc);
+                    cur = dg;
+                    acc = 0ull;
+                }
+                acc += (1ull << CSHIFT) + (m & LOW);
+            }
+        }
+    }
+    if (acc) atomicAdd(&lh[cur], acc);
+    if (L == 1 && bad) atomicAdd(&lbad, bad);
+    __syncthreads();
+    unsigned* gc = L == 1 ? w.cnt1 : L == 2 ? w.cnt2 : w.cnt3;
+    unsigned long long* gs = L == 1 ? w.sum1 : L == 2 ? w.sum2 : w.sum3;
+    for (int b = threadIdx.x; b < NB; b += PJ_NT) {
+        const unsigned long long v = lh[b];
+        if (v) {
+            atomicAdd(&gc[b], (unsigned)(v >> CSHIFT));
+            atomicAdd(&gs[b], v & ((1ull << CSHIFT) - 1));
+        }
+    }
+    if (L == 1 && threadIdx.x == 0 && lbad) atomicAdd(w.bad, lbad);
+}
+
+// xn = soft(x + c h, lam), lam the final decision (taken here from the
+// level-3 histogram when the first two levels did not finish), ct = (c, tau)
+// as the level-1 pass copied them; partials: slot 0 sum -h.(xn - x), slot 1
+// sum |xn|, slot 2 lam (block 0; 0 elsewhere). Clears the level-1 and level-2
+// histograms for the next projection.
 __global__ __launch_bounds__(SV_NT) void k_sv_soft(const float* __restrict__ x, const float* __restrict__ h,
-                                                  double c, PjState* __restrict__ st, size_t n,
+                                                  const double* __restrict__ ct, size_t n, PjWork w,
                                                   float* __restrict__ xn, double* __restrict__ part) {
     __shared__ double sh[SV_NT / 64];
-    const double L = st->lam;
-    double s0 = 0.0, s1 = 0.0;
+    __shared__ unsigned lc[PJ_BINS3];
+    __shared__ unsigned long long ls[PJ_BINS3];
+    const double c = ct[0], tau = ct[1];
+    double L;
+    const PjState s1 = *w.st1;
+    if (s1.done != 0.0) {
+        L = s1.lam;
+    } else {
+        const PjState s2 = *w.st2;
+        L = s2.done != 0.0 ? s2.lam : pj_decide<3>(w.cnt3, w.sum3, 0u, s2, tau, lc, ls).lam;
+    }
+    {
+        const size_t i = (size_t)blockIdx.x * SV_NT + threadIdx.x, all = (size_t)gridDim.x * SV_NT;
+        for (size_t b = i; b < (size_t)PJ_BINS; b += all) {
+            w.cnt1[b] = 0u;
+            w.sum1[b] = 0ull;
+            w.cnt2[b] = 0u;
+            w.sum2[b] = 0ull;
+        }
+        if (i == 0) *w.bad = 0u;
+    }
+    double s0 = 0.0, s1s = 0.0;
     const size_t n4 = n / 4, stride = (size_t)gridDim.x * SV_NT;
     for (size_t j0 = (size_t)blockIdx.x * SV_NT + threadIdx.x; j0 < n4; j0 += stride * SV_U) {
         float4 xv[SV_U], hv[SV_U];
@@ -505,7 +564,7 @@ __global__ __launch_bounds__(SV_NT) void k_sv_soft(const float* __restrict__ x, 
                 const float o = a > 0 ? (float)copysign(a, (double)v) : a <= 0 ? 0.0f : __builtin_nanf("");
                 o4[e] = o;
                 s0 += -he * ((double)o - xe);
-                s1 += fabs((double)o);
+                s1s += fabs((double)o);
             }
             const size_t j = j0 + u * stride;
             if (j < n4) reinterpret_cast<float4*>(xn)[j] = make_float4(o4[0], o4[1], o4[2], o4[3]);
@@ -513,19 +572,9 @@ __global__ __launch_bounds__(SV_NT) void k_sv_soft(const float* __restrict__ x, 
     }
     double t = block_reduce<false>(s0, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
-    t = block_reduce<false>(s1, sh);
+    t = block_reduce<false>(s1s, sh);
     if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = t;
-    if (threadIdx.x == 0) {
-        part[2 * gridDim.x + blockIdx.x] = blockIdx.x == 0 ? st->done : 0.0;
-        if (blockIdx.x == 0) st->done = 0.0;   // the next projection starts at the first pass
-    }
-}
-
-__global__ void k_sv_zero(PjState* __restrict__ p, unsigned* __restrict__ ticket) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *p = PjState{0.0, 0.0, 0.0, 0.0, 0u, 0u};
-        *ticket = 0u;
-    }
+    if (threadIdx.x == 0) part[2 * gridDim.x + blockIdx.x] = blockIdx.x == 0 ? L : 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_sv_fill(float* __restrict__ v, size_t n, float val) {
@@ -564,17 +613,27 @@ std::vector<double> ring_cubic_basis(int N) {
 namespace {
 
 struct SolveWork {
-    std::vector<void*> allocs;
+    std::vector<void*> allocs, host_allocs;
     float *x = nullptr, *xn = nullptr, *h = nullptr, *hn = nullptr;
     float *z = nullptr, *r = nullptr, *rn = nullptr, *bt = nullptr;
-    double *m = nullptr, *ring = nullptr, *Q = nullptr, *part = nullptr, *fin = nullptr;
-    rn::PjState* pst = nullptr;     // projection threshold state
-    unsigned* hcnt = nullptr;       // projection histogram: counts, PJ_BINS
-    unsigned long long* hsum = nullptr;   // and significand sums below the digit, PJ_BINS
-    unsigned* hbad = nullptr;       // count of non-finite v
-    unsigned* ticket = nullptr;    // last-block ticket of the projection steps
+    double *m = nullptr, *ring = nullptr, *Q = nullptr, *part = nullptr;
+    // fin_h: pinned, coherent host memory the fold kernel writes each read's
+    // sums to; ct: the projection's step and radius for its later launches
+    double *fin_h = nullptr, *ct = nullptr;
+    // l1 projection: histograms of the three levels (counts, sums), the
+    // non-finite count, the decisions after levels 1 and 2
+    static constexpr size_t PJ_ALL = 2 * (size_t)rn::PJ_BINS + rn::PJ_BINS3;
+    unsigned* pjc = nullptr;
+    unsigned long long* pjs = nullptr;
+    unsigned* pjbad = nullptr;
+    rn::PjState* pjst = nullptr;
+    rn::PjWork pj() const {
+        return rn::PjWork{pjc, pjc + rn::PJ_BINS, pjc + 2 * rn::PJ_BINS, pjs, pjs + rn::PJ_BINS,
+                          pjs + 2 * rn::PJ_BINS, pjbad, pjst, pjst + 1};
+    }
     ~SolveWork() {
         for (void* p : allocs) (void)hipFree(p);
+        for (void* p : host_allocs) (void)hipHostFree(p);
     }
     template <class T>
     bool alloc(T** out, size_t count) {
@@ -587,14 +646,24 @@ struct SolveWork {
         *out = static_cast<T*>(p);
         return true;
     }
+    bool alloc_host(double** out, size_t count) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(double) * count, hipHostMallocCoherent) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        host_allocs.push_back(p);
+        *out = static_cast<double*>(p);
+        return true;
+    }
 };
 
 std::vector<double> cubic_basis(int N) { return rn::ring_cubic_basis(N); }
 
 // fin slots: 0-1 residual (sum r^2, sum r.b~), 2-4 projection (g.dx, ||xn||_1,
-// converged flag), 5-8 spectral step (sum s^2, sum s.y, max |hn|, ||xn||_1)
+// the threshold lam), 5-8 spectral step (sum s^2, sum s.y, max |hn|, ||xn||_1)
 constexpr int FIN_RES = 0, FIN_PROJ = 2, FIN_BB = 5, FIN_COUNT = 9;
-constexpr unsigned FIN_MAX_OPS = (1u << (FIN_PROJ + 2)) | (1u << (FIN_BB + 2));   // the max slots
+constexpr unsigned FIN_MAX_OPS = 1u << (FIN_BB + 2);   // the max slot
 static_assert(FIN_COUNT <= rn::SV_FIN_SLOTS, "fin slots");
 
 struct Solver {
@@ -611,16 +680,22 @@ struct Solver {
     void chk(hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; }
 
     double* part(int slot) { return w.part + (size_t)slot * rn::SV_BLOCKS; }
-    // fold the per-block partials of every slot into fin and read fin back
-    // (one launch, one host wait; slots no kernel wrote since the last read
-    // hold their earlier partials)
-    bool read(double* out) {
-        hipLaunchKernelGGL(rn::k_sv_final, dim3(1), dim3(rn::SV_NT), 0, st, w.part, rn::SV_BLOCKS, FIN_COUNT,
-                           FIN_MAX_OPS, w.fin);
+    // fold the per-block partials of every slot into the host's fin (slots no
+    // kernel wrote since the last fold hold their earlier partials)
+    void fold() {
+        hipLaunchKernelGGL(rn::k_sv_final, dim3(1), dim3(rn::SV_NT), 0, st, w.part, FIN_COUNT, FIN_MAX_OPS, w.fin_h);
         chk(hipGetLastError());
-        chk(hipMemcpyAsync(out, w.fin, sizeof(double) * FIN_COUNT, hipMemcpyDeviceToHost, st));
+    }
+    // wait for the stream and copy fin out
+    bool wait(double* out) {
         chk(hipStreamSynchronize(st));
-        return err == hipSuccess;
+        if (err != hipSuccess) return false;
+        std::copy(w.fin_h, w.fin_h + FIN_COUNT, out);
+        return true;
+    }
+    bool read(double* out) {
+        fold();
+        return wait(out);
     }
 
     // r = F(b - z) (z may be null) -> fin[0] = sum r^2, fin[1] = sum r.bt (bt may be null)
@@ -637,16 +712,16 @@ struct Solver {
         chk(hipGetLastError());
     }
 
-    // xn = P_tau(x + c h) -> fin[2] = sum -h.(xn - x), fin[3] = ||xn||_1,
-    // fin[4] = 1 (the threshold is final after the three passes)
+    // xn = P_tau(x + c h) -> fin[2] = sum -h.(xn - x), fin[3] = ||xn||_1, fin[4] = lam
     void project(const float* x, const float* h, double c, double tau, float* xn) {
-        hipLaunchKernelGGL(rn::k_sv_pj_pass<1>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, n2, w.pst,
-                           w.hcnt, w.hsum, w.hbad, w.ticket);
-        hipLaunchKernelGGL(rn::k_sv_pj_pass<2>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, n2, w.pst,
-                           w.hcnt, w.hsum, w.hbad, w.ticket);
-        hipLaunchKernelGGL(rn::k_sv_pj_pass<3>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, n2, w.pst,
-                           w.hcnt, w.hsum, w.hbad, w.ticket);
-        hipLaunchKernelGGL(rn::k_sv_soft, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, h, c, w.pst, n2, xn,
+        const rn::PjWork pw = w.pj();
+        hipLaunchKernelGGL(rn::k_sv_pj_pass<1>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, c, tau, w.ct, n2,
+                           pw);
+        hipLaunchKernelGGL(rn::k_sv_pj_pass<2>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, 0.0, 0.0, w.ct, n2,
+                           pw);
+        hipLaunchKernelGGL(rn::k_sv_pj_pass<3>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, x, h, 0.0, 0.0, w.ct, n2,
+                           pw);
+        hipLaunchKernelGGL(rn::k_sv_soft, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, x, h, w.ct, n2, pw, xn,
                            part(FIN_PROJ));
         chk(hipGetLastError());
     }
@@ -657,16 +732,17 @@ struct Solver {
         chk(hipGetLastError());
     }
 
-    // project and read fin back; fin[4] != 1 would be an internal error
+    // project and read fin back
     bool project_sync(const float* x, const float* h, double c, double tau, float* xn, double* fin) {
         project(x, h, c, tau, xn);
-        return read(fin) && projected(fin);
+        return read(fin);
     }
-    bool projected(const double* fin) {
-        if (fin[FIN_PROJ + 2] == 1.0) return true;
-        err = hipErrorUnknown;
-        rn::api_fail(RADON_ERR_DEVICE, "radon_solve_bpdn: the l1 projection did not finish");
-        return false;
+    // clear the projection histograms (every projection leaves them cleared;
+    // this covers a run that follows one that stopped early)
+    void reset_projection() {
+        chk(hipMemsetAsync(w.pjc, 0, sizeof(unsigned) * SolveWork::PJ_ALL, st));
+        chk(hipMemsetAsync(w.pjs, 0, sizeof(unsigned long long) * SolveWork::PJ_ALL, st));
+        chk(hipMemsetAsync(w.pjbad, 0, sizeof(unsigned), st));
     }
 
     bool forward(const float* x, float* z) {
@@ -677,6 +753,17 @@ struct Solver {
         ++na;
         return radon_adjoint(plan, r, h, st) == RADON_OK;
     }
+
+    // One line-search trial: xn = P_tau(x + c h), r_n = F(b - A xn),
+    // h_n = A^T r_n, the spectral sums, and fin read back (one host wait)
+    bool trial(double c, double tau, double* fin) {
+        project(w.x, w.h, c, tau, w.xn);
+        if (!forward(w.xn, w.z)) return false;
+        residual(w.z, w.rn, w.bt);
+        if (!adjoint(w.rn, w.hn)) return false;
+        bb(w.x, w.xn, w.h, w.hn);
+        return read(fin);
+    }
 };
 
 }  // namespace
@@ -686,7 +773,7 @@ extern "C" radon_status_t radon_ring_filter(radon_plan_t plan, const float* y_de
     const rn::Plan& p = plan->p;
     SolveWork w;
     if (!w.alloc(&w.m, p.n_det) || !w.alloc(&w.ring, p.n_det) || !w.alloc(&w.Q, (size_t)p.n_det * 4) ||
-        !w.alloc(&w.part, (size_t)rn::SV_SLOTS * rn::SV_BLOCKS) || !w.alloc(&w.fin, rn::SV_SLOTS))
+        !w.alloc(&w.part, (size_t)rn::SV_SLOTS * rn::SV_BLOCKS))
         return RADON_ERR_OOM;
     hipStream_t st = (hipStream_t)stream;
     const std::vector<double> Q = cubic_basis(p.n_det);
@@ -699,6 +786,53 @@ extern "C" radon_status_t radon_ring_filter(radon_plan_t plan, const float* y_de
                        p.n_views, p.n_det, out_dev, w.part);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return RADON_ERR_DEVICE;
     return RADON_OK;
+}
+
+// ------------------------------------------------------------------ l1-ball projection
+
+extern "C" radon_status_t radon_project_l1(const float* v_dev, int64_t n, double tau, float* out_dev,
+                                           double* lam_host, void* stream) {
+    if (n < 0 || n % 4) return rn::api_fail(RADON_ERR_INVALID, "radon_project_l1: n must be a multiple of 4, >= 0");
+    if (!(tau >= 0) || !std::isfinite(tau))
+        return rn::api_fail(RADON_ERR_INVALID, "radon_project_l1: tau must be finite and >= 0");
+    if (n > ((int64_t)1 << 29)) return rn::api_fail(RADON_ERR_UNSUPPORTED, "radon_project_l1: n exceeds 2^29");
+    if (n > 0 && (!v_dev || !out_dev)) return rn::api_fail(RADON_ERR_INVALID, "radon_project_l1: NULL buffer");
+    if (((uintptr_t)v_dev | (uintptr_t)out_dev) % 16)
+        return rn::api_fail(RADON_ERR_INVALID, "radon_project_l1: buffers must be 16-byte aligned");
+    if (lam_host) *lam_host = 0.0;
+    if (n == 0) return rn::api_ok();
+    SolveWork w;
+    if (!w.alloc(&w.part, (size_t)FIN_COUNT * rn::SV_BLOCKS) || !w.alloc(&w.ct, 2) ||
+        !w.alloc(&w.pjc, SolveWork::PJ_ALL) || !w.alloc(&w.pjs, SolveWork::PJ_ALL) || !w.alloc(&w.pjbad, 1) ||
+        !w.alloc(&w.pjst, 2) || !w.alloc_host(&w.fin_h, FIN_COUNT))
+        return rn::api_fail(RADON_ERR_OOM, "radon_project_l1: workspace allocation failed");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemsetAsync(w.part, 0, sizeof(double) * FIN_COUNT * rn::SV_BLOCKS, st);
+    if (e == hipSuccess) e = hipMemsetAsync(w.pjc, 0, sizeof(unsigned) * SolveWork::PJ_ALL, st);
+    if (e == hipSuccess) e = hipMemsetAsync(w.pjs, 0, sizeof(unsigned long long) * SolveWork::PJ_ALL, st);
+    if (e == hipSuccess) e = hipMemsetAsync(w.pjbad, 0, sizeof(unsigned), st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return rn::api_fail(RADON_ERR_DEVICE, "radon_project_l1: clearing the workspace failed");
+    }
+    // the solver's projection of x + c h with x = h = v, c = 0 (v + 0 v = v for finite v)
+    const size_t nn = (size_t)n;
+    const rn::PjWork pw = w.pj();
+    hipLaunchKernelGGL(rn::k_sv_pj_pass<1>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, v_dev, v_dev, 0.0, tau, w.ct,
+                       nn, pw);
+    hipLaunchKernelGGL(rn::k_sv_pj_pass<2>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, v_dev, v_dev, 0.0, 0.0, w.ct,
+                       nn, pw);
+    hipLaunchKernelGGL(rn::k_sv_pj_pass<3>, dim3(rn::PJ_BLOCKS), dim3(rn::PJ_NT), 0, st, v_dev, v_dev, 0.0, 0.0, w.ct,
+                       nn, pw);
+    hipLaunchKernelGGL(rn::k_sv_soft, dim3(rn::SV_BLOCKS), dim3(rn::SV_NT), 0, st, v_dev, v_dev, w.ct, nn, pw,
+                       out_dev, w.part + (size_t)FIN_PROJ * rn::SV_BLOCKS);
+    hipLaunchKernelGGL(rn::k_sv_final, dim3(1), dim3(rn::SV_NT), 0, st, w.part, FIN_COUNT, FIN_MAX_OPS, w.fin_h);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        return rn::api_fail(RADON_ERR_DEVICE, "radon_project_l1: launch failed");
+    }
+    if (lam_host) *lam_host = w.fin_h[FIN_PROJ + 2];
+    return rn::api_ok();
 }
 
 // ------------------------------------------------------------------ ring filter without allocation
@@ -803,8 +937,7 @@ radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, 
     hipStream_t st = S.st;
     double fin[FIN_COUNT];
     out = RunOut{};
-    // projection state: threshold 0 (no warm start yet), ticket 0
-    hipLaunchKernelGGL(rn::k_sv_zero, dim3(1), dim3(64), 0, st, w.pst, w.ticket);
+    S.reset_projection();
     // start point, tau = ||x0||_1, and the projection of x0 (a no-op at that radius)
     if (!warm) hipLaunchKernelGGL(rn::k_sv_fill, dim3(1024), dim3(256), 0, st, w.x, S.n2, 0.0f);
     S.bb(nullptr, w.x, nullptr, w.x);
@@ -875,12 +1008,7 @@ radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, 
         const double fmax = *std::max_element(fs.begin(), fs.end());
         double step = 1.0, fn = 0, rbtn = 0;
         while (true) {
-            S.project(w.x, w.h, step * alpha, tau, w.xn);
-            if (!S.forward(w.xn, w.z)) return RADON_ERR_DEVICE;
-            S.residual(w.z, w.rn, w.bt);
-            if (!S.adjoint(w.rn, w.hn)) return RADON_ERR_DEVICE;
-            S.bb(w.x, w.xn, w.h, w.hn);
-            if (!S.read(fin) || !S.projected(fin)) return RADON_ERR_DEVICE;
+            if (!S.trial(step * alpha, tau, fin)) return RADON_ERR_DEVICE;
             const double gtd = fin[FIN_PROJ];
             fn = 0.5 * fin[FIN_RES];
             rbtn = fin[FIN_RES + 1];
@@ -926,20 +1054,16 @@ extern "C" radon_status_t radon_solve_bpdn(radon_plan_t plan, const float* b_dev
     if (!w.alloc(&w.x, n2) || !w.alloc(&w.xn, n2) || !w.alloc(&w.h, n2) || !w.alloc(&w.hn, n2) ||
         !w.alloc(&w.z, ns) || !w.alloc(&w.r, ns) || !w.alloc(&w.rn, ns) || !w.alloc(&w.bt, ns) ||
         !w.alloc(&w.m, p.n_det) || !w.alloc(&w.ring, p.n_det) || !w.alloc(&w.Q, (size_t)p.n_det * 4) ||
-        !w.alloc(&w.part, (size_t)FIN_COUNT * rn::SV_BLOCKS) || !w.alloc(&w.fin, FIN_COUNT) ||
-        !w.alloc(&w.pst, 1) || !w.alloc(&w.hcnt, rn::PJ_BINS) || !w.alloc(&w.hsum, rn::PJ_BINS) ||
-        !w.alloc(&w.hbad, 1) || !w.alloc(&w.ticket, 1))
+        !w.alloc(&w.part, (size_t)FIN_COUNT * rn::SV_BLOCKS) || !w.alloc(&w.ct, 2) ||
+        !w.alloc(&w.pjc, SolveWork::PJ_ALL) || !w.alloc(&w.pjs, SolveWork::PJ_ALL) || !w.alloc(&w.pjbad, 1) ||
+        !w.alloc(&w.pjst, 2) || !w.alloc_host(&w.fin_h, FIN_COUNT))
         return RADON_ERR_OOM;
     hipStream_t st = (hipStream_t)stream;
     Solver S{plan, p, w, st, opts->ring_filter != 0, b_dev, n2, ns};
     const std::vector<double> Q = cubic_basis(p.n_det);
     S.chk(hipMemcpyAsync(w.Q, Q.data(), sizeof(double) * Q.size(), hipMemcpyHostToDevice, st));
-    // every read folds all partial slots, also those no kernel has written yet;
-    // the projection passes leave their histogram cleared, so it starts cleared
+    // every read folds all partial slots, also those no kernel has written yet
     S.chk(hipMemsetAsync(w.part, 0, sizeof(double) * FIN_COUNT * rn::SV_BLOCKS, st));
-    S.chk(hipMemsetAsync(w.hcnt, 0, sizeof(unsigned) * rn::PJ_BINS, st));
-    S.chk(hipMemsetAsync(w.hsum, 0, sizeof(unsigned long long) * rn::PJ_BINS, st));
-    S.chk(hipMemsetAsync(w.hbad, 0, sizeof(unsigned), st));
 
     double fin[FIN_COUNT];
     // b~ = F b and its norm

@@ -51,6 +51,7 @@ _SIGS = {
     "radon_ring_filter": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_ring_filter_noalloc": (_c_int, [_vp, _vp, _vp, _vp]),
     "radon_solve_bpdn": (_c_int, [_vp, _vp, _vp, ctypes.c_void_p, ctypes.c_void_p, _vp]),
+    "radon_project_l1": (_c_int, [_vp, _c_i64, _c_dbl, _vp, ctypes.POINTER(_c_dbl), _vp]),
     "radon_plan_tuned": (_c_int, [ctypes.POINTER(_vp), _c_int, ctypes.POINTER(_c_dbl), _c_int, _c_int, _c_dbl,
                                   _c_int, ctypes.c_void_p]),
     "radon_plan_tuning": (_c_int, [_vp, ctypes.c_void_p]),
@@ -126,7 +127,7 @@ def declared_functions(header: str = HEADER_PATH):
     """Names of the functions that include/radon.h declares."""
     text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(radon_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(radon_[a-z0-9_]+)\s*\(", text)))
 
 
 def _check(status: int, what: str):
@@ -373,6 +374,21 @@ def fft_test(x, inverse: bool = False, stream=None):
                                 ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                 _stream_ptr(stream)), "radon_fft_test")
     return out
+
+
+def project_l1(v, tau: float, stream=None):
+    """Euclidean projection of a float32 device tensor (contiguous, numel a
+    multiple of 4) onto {||x||_1 <= tau}; returns (projection, lam), the
+    projection sign(v) max(|v| - lam, 0) in v's shape."""
+    torch = _torch()
+    flat = v.reshape(-1)
+    _dev_ptr(flat, (flat.numel(),), "v")
+    out = torch.empty_like(v)
+    lam = ctypes.c_double(0.0)
+    _check(lib().radon_project_l1(ctypes.c_void_p(flat.data_ptr()), int(flat.numel()), float(tau),
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.byref(lam), _stream_ptr(stream)),
+           "radon_project_l1")
+    return out, lam.value
 
 
 def autotune(n: int, angles, n_det: int, sigma: float = 2.0, W: int = 6, repeats: int = 5, stream=None):

@@ -91,3 +91,22 @@ def test_null_plan_calls():
     L.radon_plan_destroy(None)   # NULL-safe
     assert L.radon_fft_test(2562, 1, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == rb.RADON_ERR_UNSUPPORTED
     assert L.radon_fft_test(64, 0, 0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == rb.RADON_ERR_INVALID
+
+
+def test_project_l1_argument_errors():
+    """radon_project_l1 rejects bad arguments before touching a device; n = 0
+    is a no-op that returns lam = 0."""
+    L = rb.lib()
+    lam = ctypes.c_double(-1.0)
+    p = ctypes.c_void_p(256)   # never dereferenced: every call below fails its checks first
+    assert L.radon_project_l1(p, 6, 1.0, p, ctypes.byref(lam), None) == rb.RADON_ERR_INVALID      # n % 4
+    assert L.radon_project_l1(p, -4, 1.0, p, ctypes.byref(lam), None) == rb.RADON_ERR_INVALID     # n < 0
+    assert L.radon_project_l1(p, 8, -1.0, p, ctypes.byref(lam), None) == rb.RADON_ERR_INVALID     # tau < 0
+    assert L.radon_project_l1(p, 8, float("nan"), p, None, None) == rb.RADON_ERR_INVALID
+    assert L.radon_project_l1(p, 8, float("inf"), p, None, None) == rb.RADON_ERR_INVALID
+    assert L.radon_project_l1(None, 8, 1.0, p, None, None) == rb.RADON_ERR_INVALID                # NULL
+    assert L.radon_project_l1(ctypes.c_void_p(260), 8, 1.0, p, None, None) == rb.RADON_ERR_INVALID  # misaligned
+    assert L.radon_project_l1(p, (1 << 29) + 4, 1.0, p, None, None) == rb.RADON_ERR_UNSUPPORTED
+    assert rb.lib().radon_last_error() != b""
+    assert L.radon_project_l1(None, 0, 1.0, None, ctypes.byref(lam), None) == rb.RADON_OK
+    assert lam.value == 0.0

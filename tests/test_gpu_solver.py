@@ -3,6 +3,7 @@
 L1 minimisers need not be unique, so solves are compared by what is unique:
 the residual norm at the solution (= sigma) and the optimal l1 norm.
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -11,6 +12,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle.grid import grid_adjoint, grid_forward  # noqa: E402
+from oracle.solver import project_l1 as oracle_project_l1  # noqa: E402
 from oracle.solver import ring_filter, spgl1_bpdn  # noqa: E402
 from radon_inputs import config1_phantom, random_sinogram, uniform_angles  # noqa: E402
 
@@ -19,7 +21,8 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_1009_1380_amd import Plan  # noqa: E402
+from paper_1009_1380_amd import Plan, project_l1  # noqa: E402
+from paper_1009_1380_amd import radon as rb  # noqa: E402
 
 DEV = "cuda:0"
 
@@ -177,3 +180,70 @@ def test_warm_start_above_root_reaches_cold_l1():
     assert sw["status"] == 2 and sw["fallback"] == 0
     assert abs(sw["rnorm"] - sigma) <= 2e-5 * sigma
     assert abs(sw["x_l1"] - sc["x_l1"]) <= 2e-3 * sc["x_l1"]
+
+
+def _l1_vector(kind, n, rng):
+    if kind == "normal":
+        v = rng.normal(size=n)
+    elif kind == "cauchy":
+        v = rng.standard_cauchy(size=n) * 1e3
+    elif kind == "duplicates":
+        v = np.round(rng.normal(size=n) * 4) / 4
+    elif kind == "denormal":
+        v = rng.normal(size=n) * 1e-40
+    elif kind == "decades":
+        v = np.exp(rng.normal(size=n) * 8) * rng.choice([-1.0, 1.0], n)
+    else:   # half zeros
+        v = rng.normal(size=n)
+        v[rng.random(n) < 0.5] = 0
+    return v.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [4, 5120, 1024 * 1024, 3 * 2 ** 20 + 12])
+@pytest.mark.parametrize("kind", ["normal", "cauchy", "duplicates", "denormal", "decades", "zeros"])
+def test_project_l1_vs_oracle(kind, n):
+    """The radix-select l1-ball projection against the oracle's sort-based
+    one, for every regime of tau: 0 (all zero), inside the range, equal to
+    and above sum |v| (v unchanged, lam = 0); sizes from one 16-byte piece to
+    several grid-stride rounds."""
+    note(f"l1 projection {kind} n={n}")
+    rng = np.random.default_rng(n + len(kind))
+    v = _l1_vector(kind, n, rng)
+    v64 = v.astype(np.float64)
+    a = np.abs(v64)
+    vd = to_dev(v)
+    for frac in (0.0, 1e-6, 0.01, 0.3, 0.9, 1.0, 1.5):
+        tau = frac * float(a.sum())
+        out, lam = project_l1(vd, tau)
+        out = out.cpu().numpy().astype(np.float64)
+        ref = oracle_project_l1(v64, tau)
+        assert np.max(np.abs(out - ref)) <= 2e-7 * a.max() + 1e-45, (frac, lam)
+        if frac == 0.0:
+            assert not out.any()
+        elif frac > 1.0:
+            assert lam == 0.0 and np.array_equal(out, v64)
+        elif frac == 1.0:   # tau equals sum |v| only up to the order of the sums
+            assert lam <= 1e-12 * a.max()
+        else:
+            # lam is the root of sum max(|v| - lam, 0) = tau (float64 sums)
+            assert lam > 0 and abs(np.maximum(a - lam, 0).sum() - tau) <= 1e-9 * tau
+    # in place, and deterministic
+    tau = 0.3 * float(a.sum())
+    o1, l1 = project_l1(vd, tau)
+    w = vd.clone()
+    o2, l2 = project_l1(w, tau)
+    assert torch.equal(o1, o2) and l1 == l2
+    lamc = ctypes.c_double()
+    rb._check(rb.lib().radon_project_l1(ctypes.c_void_p(w.data_ptr()), n, tau, ctypes.c_void_p(w.data_ptr()),
+                                        ctypes.byref(lamc), rb._stream_ptr(None)), "radon_project_l1")
+    assert torch.equal(w, o1) and lamc.value == l1
+
+
+def test_project_l1_nonfinite():
+    """A NaN or infinite entry gives lam = NaN and NaN everywhere."""
+    note("l1 projection, non-finite input")
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        v = np.random.default_rng(1).normal(size=4096).astype(np.float32)
+        v[1234] = bad
+        out, lam = project_l1(to_dev(v), 10.0)
+        assert np.isnan(lam) and torch.isnan(out).all()
