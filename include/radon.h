@@ -282,9 +282,10 @@ typedef struct {
     double dec_tol;    /* stall test that triggers the Newton step on tau (1e-4)          */
     int max_iter;      /* iteration limit                                                  */
     int ring_filter;   /* 1: operator F A and data F b; 0: F = identity                    */
-    int warm_start;    /* 1: x_dev holds the starting image and tau0 = ||x0||_1; 0: x0 = 0 */
-    int fallback_iters;/* warm start: iterations without a new least residual before the
-                          cold solver takes over (<= 0: 100)                              */
+    int warm_start;    /* 1: x_dev holds the starting image (tau0: see radon_solve_bpdn);
+                          0: x0 = 0                                                        */
+    int fallback_iters;/* warm start: iterations without a new least | ||r|| - sigma |
+                          before the cold solver takes over (<= 0: 100)                   */
 } radon_solve_opts;
 
 typedef struct {
@@ -307,7 +308,7 @@ enum {
     RADON_FALLBACK_NONFINITE = 1,        /* start, its l1 norm, residual or objective not finite  */
     RADON_FALLBACK_WORSE_THAN_ZERO = 2,  /* ||F(A x0 - b)|| >= ||F b||: x0 fits no better than 0 */
     RADON_FALLBACK_ITER_LIMIT = 3,       /* the warm run reached max_iter                          */
-    RADON_FALLBACK_STALLED = 4           /* no new least residual within fallback_iters iterations */
+    RADON_FALLBACK_STALLED = 4           /* no new least | ||r|| - sigma | in fallback_iters iterations */
 };
 
 /*
@@ -325,10 +326,12 @@ enum {
  * abandoned for a cold one (stats->fallback says why) when x0 or its first
  * residual is not finite, when x0 fits the data no better than zero, when it
  * reaches max_iter, or when fallback_iters iterations pass without a new
- * least residual. A warm start may lie above the root of the Pareto curve,
- * where a point with ||r|| = sigma need not have the least l1 norm, so a warm
- * run stops at the root only after its first Newton update of tau (which,
- * the curve being convex and decreasing, leaves tau at or below the root).
+ * least distance | ||r|| - sigma |. Above the root of the Pareto curve a
+ * point with ||r|| = sigma need not have the least l1 norm, so a warm run
+ * starts at tau0 = min(||x0||_1, max(0, D)), D = (r.F b - sigma ||r||) /
+ * ||A^T r||_inf for x0's residual r: by weak duality D <= tau*, and from
+ * below the root the run proceeds as a cold one does (x0 is projected onto
+ * the tau0 ball; D <= 0 makes it a cold start).
  * Errors: RADON_ERR_INVALID for NULL pointers, sigma < 0 or not finite,
  * opt_tol <= 0, max_iter < 1, a non-finite sinogram, or a cold run whose
  * objective becomes non-finite; RADON_ERR_OOM when the workspace cannot be

@@ -918,16 +918,16 @@ struct RunOut {
     int fallback = 0;     // why a warm run was abandoned (RADON_FALLBACK_*), 0 if it was not
 };
 
-// One SPGL1 run. `warm`: w.x holds the start image (tau0 = its l1 norm), else
-// the run starts from zero. A warm run is abandoned, and reports why in
-// out.fallback, when its start is non-finite, when it fits the data no better
-// than x = 0, when its residual norm stops decreasing for `stall_iters`
+// One SPGL1 run. `warm`: w.x holds the start image, else the run starts from
+// zero. A warm run is abandoned, and reports why in out.fallback, when its
+// start is non-finite, when it fits the data no better than x = 0, when
+// | ||r|| - sigma | has not reached a new least value for `stall_iters`
 // iterations, or when it reaches the iteration limit; the caller then runs
-// cold. A warm start may lie above the Pareto root (tau0 > tau*), where a
-// point with ||r|| = sigma need not have the least l1 norm; such a run is
-// not allowed to stop at the root before its first Newton update of tau,
-// which (the Pareto curve being convex and decreasing) leaves tau at or
-// below the root, as a cold run's tau always is.
+// cold. Above the Pareto root (tau > tau*) a point with ||r|| = sigma need not
+// have the least l1 norm, so a warm run does not start at tau = ||x0||_1 but
+// at the lower bound on tau* that x0's residual gives by weak duality: from
+// there it approaches the root from below, as a cold run does, under the same
+// tests.
 radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, bool warm, double bnorm,
                          RunOut& out) {
     const double sigma = opts->sigma, opt_tol = opts->opt_tol, bp_tol = opts->bp_tol, dec_tol = opts->dec_tol;
@@ -938,31 +938,46 @@ radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, 
     double fin[FIN_COUNT];
     out = RunOut{};
     S.reset_projection();
+    double f = 0, rbt = 0, gnorm = 0;
+    // x = P_tau(x), then r = F(b - A x), h = A^T r and their sums
+    auto shrink_to = [&](double t) -> bool {
+        if (!S.project_sync(w.x, w.x, 0.0, t, w.xn, fin)) return false;
+        std::swap(w.x, w.xn);
+        if (!S.forward(w.x, w.z)) return false;
+        S.residual(w.z, w.r, w.bt);
+        if (!S.adjoint(w.r, w.h)) return false;
+        S.bb(nullptr, w.x, nullptr, w.h);
+        if (!S.read(fin)) return false;
+        f = 0.5 * fin[FIN_RES];
+        rbt = fin[FIN_RES + 1];
+        gnorm = fin[FIN_BB + 2];
+        return true;
+    };
     // start point, tau = ||x0||_1, and the projection of x0 (a no-op at that radius)
     if (!warm) hipLaunchKernelGGL(rn::k_sv_fill, dim3(1024), dim3(256), 0, st, w.x, S.n2, 0.0f);
     S.bb(nullptr, w.x, nullptr, w.x);
     if (!S.read(fin)) return RADON_ERR_DEVICE;
     double tau = fin[FIN_BB + 3];
     if (warm && !std::isfinite(tau)) { out.fallback = RADON_FALLBACK_NONFINITE; return RADON_OK; }
-    if (!S.project_sync(w.x, w.x, 0.0, tau, w.xn, fin)) return RADON_ERR_DEVICE;
-    std::swap(w.x, w.xn);
-    // r = F(b - A x), h = A^T r
-    if (!S.forward(w.x, w.z)) return RADON_ERR_DEVICE;
-    S.residual(w.z, w.r, w.bt);
-    if (!S.adjoint(w.r, w.h)) return RADON_ERR_DEVICE;
-    S.bb(nullptr, w.x, nullptr, w.h);
-    if (!S.read(fin)) return RADON_ERR_DEVICE;
-    double f = 0.5 * fin[FIN_RES], rbt = fin[FIN_RES + 1];
-    double gnorm = fin[FIN_BB + 2];
+    if (!shrink_to(tau)) return RADON_ERR_DEVICE;
     if (warm) {
         if (!std::isfinite(f) || !std::isfinite(gnorm)) { out.fallback = RADON_FALLBACK_NONFINITE; return RADON_OK; }
         if (sqrt(2 * f) >= bnorm) { out.fallback = RADON_FALLBACK_WORSE_THAN_ZERO; return RADON_OK; }
+        // start below the root: y = r / ||A^T r||_inf is dual feasible, so weak
+        // duality bounds the optimal l1 norm from below by
+        // D = (r.b~ - sigma ||r||) / ||A^T r||_inf; the run starts at
+        // tau0 = D clamped to [0, ||x0||_1], with x0 projected onto that ball
+        const double D = gnorm > 0 ? (rbt - sigma * sqrt(2 * f)) / gnorm : 0.0;
+        const double tau0 = std::min(std::max(D, 0.0), tau);
+        if (tau0 < tau) {
+            tau = tau0;
+            if (!shrink_to(tau)) return RADON_ERR_DEVICE;
+        }
     }
     std::vector<double> fs(n_mem, f);
     double alpha = std::min(std::max(gnorm > 0 ? 1.0 / gnorm : 1.0, bb_min), bb_max);
-    double f_old = INFINITY, f_best = f;
+    double f_old = INFINITY, d_best = INFINITY;   // least | ||r|| - sigma | so far
     int it_best = 0;
-    bool newton_taken = !warm || tau == 0.0;   // a start at zero lies below the root
     int status = 0, it = 0;
     for (it = 1; it <= opts->max_iter; ++it) {
         const double rnorm = sqrt(2 * f);
@@ -973,10 +988,12 @@ radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, 
         const double rerr2 = fabs(f - 0.5 * sigma * sigma) / std::max(1.0, f);
         if (rgap <= std::max(opt_tol, rerr2) || rerr1 <= opt_tol) {
             if (rnorm <= bp_tol * bnorm) { status = 1; break; }
-            if (rerr1 <= opt_tol && newton_taken) { status = 2; break; }
+            if (rerr1 <= opt_tol) { status = 2; break; }
         }
         if (warm) {
-            if (f < f_best) { f_best = f; it_best = it; }
+            // progress of the root finding from either side: a start above the
+            // root lets ||r|| grow to sigma, one below lets it shrink
+            if (fabs(aerr1) < d_best) { d_best = fabs(aerr1); it_best = it; }
             else if (it - it_best >= stall_iters) { out.fallback = RADON_FALLBACK_STALLED; break; }
         }
         const double change = fabs(f - f_old);
@@ -985,20 +1002,10 @@ radon_status_t spgl1_run(Solver& S, SolveWork& w, const radon_solve_opts* opts, 
         if (stalled && gnorm > 0) {
             const double tau_old = tau;
             tau = std::max(0.0, tau + rnorm * aerr1 / gnorm);   // Newton step on the Pareto curve
-            newton_taken = true;
             if (tau < tau_old) {
                 // the ball shrank: restart from the projected iterate with its
                 // own residual and gradient
-                if (!S.project_sync(w.x, w.x, 0.0, tau, w.xn, fin)) return RADON_ERR_DEVICE;
-                std::swap(w.x, w.xn);
-                if (!S.forward(w.x, w.z)) return RADON_ERR_DEVICE;
-                S.residual(w.z, w.r, w.bt);
-                if (!S.adjoint(w.r, w.h)) return RADON_ERR_DEVICE;
-                S.bb(nullptr, w.x, nullptr, w.h);
-                if (!S.read(fin)) return RADON_ERR_DEVICE;
-                f = 0.5 * fin[FIN_RES];
-                rbt = fin[FIN_RES + 1];
-                gnorm = fin[FIN_BB + 2];
+                if (!shrink_to(tau)) return RADON_ERR_DEVICE;
             }
             std::fill(fs.begin(), fs.end(), f);
         }

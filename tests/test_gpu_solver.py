@@ -167,6 +167,26 @@ def test_warm_start_fallback_iteration_limit():
     assert torch.equal(xw, xc) and sw["iterations"] == sc["iterations"]
 
 
+def test_warm_starts_on_either_side_of_the_root():
+    """Warm starts below, at and above the solution (0.9, 1, 1.2 and 2 times
+    the cold solution) and the filtered adjoint all stop at the cold run's l1
+    norm to the tolerance of the root finding: a warm run starts at the
+    weak-duality lower bound on the optimal l1 norm, so it never approaches
+    the root from above. A start at the solution needs fewer iterations."""
+    note("warm starts on either side of the root")
+    plan, bd, sigma = _fallback_problem()
+    xc, sc = plan.solve_bpdn(bd, sigma, opt_tol=1e-3, max_iter=5000)
+    starts = {"0.9x": xc * 0.9, "1.0x": xc.clone(), "1.2x": xc * 1.2, "2x": xc * 2.0, "fbp": plan.fbp(bd)}
+    for name, x0 in starts.items():
+        xw, sw = plan.solve_bpdn(bd, sigma, x0=x0, opt_tol=1e-3, max_iter=5000)
+        note(f"{name}: {sw['iterations']} iterations (cold {sc['iterations']}), "
+             f"l1 {sw['x_l1'] / sc['x_l1'] - 1:+.2e}, fallback {sw['fallback']}")
+        assert sw["status"] == 2 and sw["fallback"] == 0
+        assert abs(sw["x_l1"] - sc["x_l1"]) <= 2e-3 * sc["x_l1"]
+        if name == "1.0x":
+            assert sw["iterations"] < sc["iterations"]
+
+
 def test_warm_start_above_root_reaches_cold_l1():
     """A start above the Pareto root (1.2 times the cold solution, so tau0 =
     1.2 tau*) must not stop at a feasible point with a larger l1 norm: the
