@@ -487,28 +487,66 @@ __device__ __forceinline__ void f4_body(int bid_, int nblk_, const float2* __res
     const float2* xa = Xr + (size_t)a0 * HQ;
     const float2* xb = Xr + (size_t)(a0 + 1) * HQ;
     const float2 zero = make_float2(0.f, 0.f);
-    // Z = A + i B, stored conjugated so the forward engine gives conj(IFFT)
-    for (int q = tid; q < ND; q += NT) {
+    const float inv = 1.0f / (float)ND;
+    // Z = A + i B at position q (A, B the two rays' Hermitian spectra), stored
+    // conjugated so the forward engine gives conj(IFFT)
+    auto zin = [&](int q, float2 ga, float2 gb) {
         float2 A, B;
         if (q == 0 || q == ND / 2) {
-            A = make_float2(xa[q].x, 0.f);
-            B = has_b ? make_float2(xb[q].x, 0.f) : zero;
+            A = make_float2(ga.x, 0.f);
+            B = make_float2(gb.x, 0.f);
         } else if (q < ND / 2) {
-            A = xa[q];
-            B = has_b ? xb[q] : zero;
+            A = ga;
+            B = gb;
         } else {
-            A = cconj(xa[ND - q]);
-            B = has_b ? cconj(xb[ND - q]) : zero;
+            A = cconj(ga);
+            B = cconj(gb);
         }
-        lds[lds_pad(q)] = make_float2(A.x - B.y, -(A.y + B.x));
-    }
-    lds_sync();
-    fft_lds<ND, 1, NT>(lds, tw, tid);
-    const float inv = 1.0f / (float)ND;
-    for (int d = tid; d < ND; d += NT) {
-        const float2 z = cconj(lds[lds_pad((d + ND / 2) % ND)]);
-        sino[(size_t)a0 * ND + d] = z.x * inv;
-        if (has_b) sino[(size_t)(a0 + 1) * ND + d] = z.y * inv;
+        return make_float2(A.x - B.y, -(A.y + B.x));
+    };
+    using IO = FftRegIO<ND, 1, NT>;
+    if constexpr (IO::NP >= 2) {
+        // the spectra are loaded straight into the first butterflies and the
+        // rays written from the last ones
+        float2 v[IO::IT0][IO::R0], Z[IO::ITL][IO::RL];
+#pragma unroll
+        for (int it = 0; it < IO::IT0; ++it) {
+            const int b = tid + it * NT;
+#pragma unroll
+            for (int m = 0; m < IO::R0; ++m) {
+                const int q = b + m * IO::NB0;
+                const int s = q <= ND / 2 ? q : ND - q;
+                const float2 ga = (b < IO::NB0) ? xa[s] : zero;
+                const float2 gb = (b < IO::NB0 && has_b) ? xb[s] : zero;
+                v[it][m] = zin(q, ga, gb);
+            }
+        }
+        fft_regs<ND, 1, NT>(v, lds, tw, tid, Z);
+#pragma unroll
+        for (int it = 0; it < IO::ITL; ++it) {
+            const int b = tid + it * NT;
+            if (b < IO::NBL) {
+#pragma unroll
+                for (int m = 0; m < IO::RL; ++m) {
+                    const int d = (b + m * IO::NBL + ND / 2) % ND;
+                    const float2 z = cconj(Z[it][m]);
+                    sino[(size_t)a0 * ND + d] = z.x * inv;
+                    if (has_b) sino[(size_t)(a0 + 1) * ND + d] = z.y * inv;
+                }
+            }
+        }
+    } else {
+        for (int q = tid; q < ND; q += NT) {
+            const int s = q <= ND / 2 ? q : ND - q;
+            lds[lds_pad(q)] = zin(q, xa[s], has_b ? xb[s] : zero);
+        }
+        lds_sync();
+        fft_lds<ND, 1, NT>(lds, tw, tid);
+        for (int d = tid; d < ND; d += NT) {
+            const float2 z = cconj(lds[lds_pad((d + ND / 2) % ND)]);
+            sino[(size_t)a0 * ND + d] = z.x * inv;
+            if (has_b) sino[(size_t)(a0 + 1) * ND + d] = z.y * inv;
+        }
     }
 }
 
@@ -526,13 +564,36 @@ __device__ __forceinline__ void a1_body(int bid_, int nblk_, const float* __rest
     __shared__ float2 lds[lds_ls(ND)];
     const int tid = threadIdx.x;
     const int a0 = bid_ * 2;
-    for (int d = tid; d < ND; d += NT) {
-        const float ya = (a0 < n_views) ? sino[(size_t)a0 * ND + d] : 0.f;
-        const float yb = (a0 + 1 < n_views) ? sino[(size_t)(a0 + 1) * ND + d] : 0.f;
-        lds[lds_pad((d + ND / 2) % ND)] = make_float2(ya, yb);
+    // the two rays as one complex line: FFT position p holds detector
+    // d = (p + ND/2) mod ND
+    using IO = FftRegIO<ND, 1, NT>;
+    if constexpr (IO::NP >= 2) {
+        // straight into the first butterflies; the other passes run in LDS,
+        // where the Hermitian split below finds both q and ND - q
+        float2 v[IO::IT0][IO::R0];
+#pragma unroll
+        for (int it = 0; it < IO::IT0; ++it) {
+            const int b = tid + it * NT;
+#pragma unroll
+            for (int m = 0; m < IO::R0; ++m) {
+                const int d = (b + m * IO::NB0 + ND / 2) % ND;
+                const float ya = (b < IO::NB0 && a0 < n_views) ? sino[(size_t)a0 * ND + d] : 0.f;
+                const float yb = (b < IO::NB0 && a0 + 1 < n_views) ? sino[(size_t)(a0 + 1) * ND + d] : 0.f;
+                v[it][m] = make_float2(ya, yb);
+            }
+        }
+        fft_first_from_regs<ND, 1, NT>(v, lds, tid);
+        lds_sync();
+        fft_passes<ND, 1, IO::R0, 1, NT, IO::LS>(lds, tw, tid);
+    } else {
+        for (int d = tid; d < ND; d += NT) {
+            const float ya = (a0 < n_views) ? sino[(size_t)a0 * ND + d] : 0.f;
+            const float yb = (a0 + 1 < n_views) ? sino[(size_t)(a0 + 1) * ND + d] : 0.f;
+            lds[lds_pad((d + ND / 2) % ND)] = make_float2(ya, yb);
+        }
+        lds_sync();
+        fft_lds<ND, 1, NT>(lds, tw, tid);
     }
-    lds_sync();
-    fft_lds<ND, 1, NT>(lds, tw, tid);
     const float sc = 0.5f / (float)ND;
     for (int q = tid; q < HQ; q += NT) {
         const float2 zq = lds[lds_pad(q)];
