@@ -327,7 +327,10 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    # the clocks take a few tens of milliseconds of load to settle: after 5
+    # warm-up pairs the first timed loop runs about 10% slow, after 100 or more
+    # it matches the per-pair median of later loops
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-views", type=int, default=1024, help="views in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the reduced-view solve timing")
@@ -404,6 +407,20 @@ def main():
     t_fwd = time_loop(lambda: plan.forward(x, out=sino, stream=stream), args.steps)
     t_adj = time_loop(lambda: plan.adjoint(sino, out=back, stream=stream), args.steps)
 
+    # per-pair spread: at least 50 back-to-back pairs with an event between
+    # consecutive pairs (warm cache, as in the solver loop)
+    n_pairs = max(50, args.steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_pairs + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for i in range(n_pairs):
+        step()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per_pair = [evs[i].elapsed_time(evs[i + 1]) for i in range(n_pairs)]
+    pair_stats = {"pairs": n_pairs, "median_ms": round(float(np.median(per_pair)), 4),
+                  "min_ms": round(float(np.min(per_pair)), 4), "max_ms": round(float(np.max(per_pair)), 4)}
+
     # cold last-level cache: a 1 GiB buffer is written before every pair (the
     # 256 MB cache then holds none of the pair's arrays); only the pair is timed
     flush = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -475,6 +492,7 @@ def main():
         "t_adj_ms": round(t_adj, 4),
         "wall_s_timed": round(wall, 4),
         "plan_s": round(t_plan, 3),
+        "ms_per_pair_warm": pair_stats,
         "ms_per_step_cold_cache": round(ms_cold, 4),
         "copy_peak_GBps": round(copy_gbs, 1),
         # the bytes this design moves per pair (Hermitian half plane, each
