@@ -114,7 +114,12 @@ void conv_wgrad(radon_cnn_s& c, Conv& L, const uint16_t* gout, const uint16_t* i
     hipLaunchKernelGGL(cnn::k_conv3x3_wgrad, grid, dim3(64), 0, st, gout, in, c.part, c.B, L.cin, L.cout, h, w);
     hipLaunchKernelGGL(cnn::k_sum_chunks, dim3((unsigned)grid1(L.nw())), dim3(256), 0, st, c.part, chunks, L.nw(),
                        L.gw);
-    hipLaunchKernelGGL(cnn::k_bias_grad, dim3(L.cout), dim3(256), 0, st, gout, c.B, L.cout, h * w, L.gb);
+    // the bias partials reuse the weight partials' buffer, which the sum above has read
+    const int bchunks = (int)((np + cnn::BG_CHUNK - 1) / cnn::BG_CHUNK);
+    hipLaunchKernelGGL(cnn::k_bias_grad, dim3((unsigned)bchunks, (unsigned)L.cout), dim3(256), 0, st, gout, c.B,
+                       L.cout, h * w, c.part);
+    hipLaunchKernelGGL(cnn::k_sum_chunks, dim3((unsigned)grid1((size_t)L.cout)), dim3(256), 0, st, c.part, bchunks,
+                       (size_t)L.cout, L.gb);
 }
 
 void pack(Conv& L, hipStream_t st) {

@@ -167,16 +167,41 @@ __global__ void k_sum_chunks(const float* __restrict__ part, int chunks, size_t 
     }
 }
 
-// Bias gradient: db[co] = sum over b, pixels of g[b, co, .] (one block per
-// channel, fixed-order block reduction).
+// Bias gradient, split over chunks of the (image, pixel) pairs:
+//   part[chunk][co] = sum over the chunk's pairs of g[b, co, p]
+// in a fixed order (per thread in index order, then a tree over the
+// threads); the chunks are summed in order by k_sum_chunks. Each thread
+// takes 8 consecutive pairs per step, as one 16-byte load when H * W is a
+// multiple of 8 (a step then never crosses an image), else one by one.
+// Grid: x = chunks, y = channels.
+constexpr int BG_CHUNK = 16384;   // pairs per chunk (a multiple of 256 * 8)
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ g, int B, int C, int HW,
-                                                  float* __restrict__ db) {
+                                                  float* __restrict__ part) {
     __shared__ float sh[256];
-    const int co = blockIdx.x;
+    const int co = blockIdx.y;
+    const long long n = (long long)B * HW;
+    const long long q0 = (long long)blockIdx.x * BG_CHUNK;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) {
-        const uint16_t* gp = g + ((size_t)b * C + co) * HW;
-        for (int e = threadIdx.x; e < HW; e += 256) s += bf2f(gp[e]);
+    for (int k = threadIdx.x * 8; k < BG_CHUNK; k += 256 * 8) {
+        const long long q = q0 + k;
+        if (HW % 8 == 0) {
+            if (q < n) {
+                const int b = (int)(q / HW);
+                const int px = (int)(q - (long long)b * HW);
+                const uint4 v = *reinterpret_cast<const uint4*>(g + ((size_t)b * C + co) * HW + px);
+                const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) s += bf2f((uint16_t)(w[j] & 0xffffu)) + bf2f((uint16_t)(w[j] >> 16));
+            }
+        } else {
+            for (int j = 0; j < 8; ++j) {
+                const long long qj = q + j;
+                if (qj < n) {
+                    const int b = (int)(qj / HW);
+                    s += bf2f(g[((size_t)b * C + co) * HW + (qj - (long long)b * HW)]);
+                }
+            }
+        }
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -184,7 +209,7 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
         if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) db[co] = sh[0];
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * C + co] = sh[0];
 }
 
 // Weights (float32 [Cout][Cin][3][3]) -> bf16 GEMM layouts for the forward

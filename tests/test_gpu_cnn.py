@@ -111,6 +111,7 @@ def test_network_forward_and_gradients_vs_reference():
     for ci, co in CHANNELS:
         nw = co * ci * 9
         assert rel(g[off:off + nw], gref[off:off + nw]) <= 5e-2, (ci, co)
+        assert rel(g[off + nw:off + nw + co], gref[off + nw:off + nw + co]) <= 5e-2, ("bias", ci, co)
         off += nw + co
     assert np.array_equal(net.get_params(), p)   # lr = 0 left the parameters alone
 
