@@ -89,29 +89,45 @@ struct radon_cnn_s {
 namespace {
 
 size_t grid1(size_t n) { return std::min<size_t>((n + 255) / 256, 65535); }
+// chunks of k_conv3x3_wgrad for B images of h x w
+size_t wgrad_chunks(long long B, int h, int w) {
+    const long long tiles = B * (long long)((h + 7) / 8) * ((w + 7) / 8);
+    return (size_t)((tiles + cnn::WT_TILES - 1) / cnn::WT_TILES);
+}
+
+// k_conv3x3 over `cout` output channels: blocks of 64 channels on 8 x 8 pixel
+// tiles, or of 32 on 16 x 8 tiles when there are at most 32
+void conv_launch(const uint16_t* in, const uint16_t* Wg, int Kp, const float* bias, const uint16_t* res,
+                 const float* res32, uint16_t* out16, float* out32, int B, int cin, int cout, int h, int w, bool relu,
+                 hipStream_t st) {
+    auto tiles = [&](int tx) { return ((w + tx - 1) / tx) * ((h + cnn::CTY - 1) / cnn::CTY); };
+    if (cout <= 32) {
+        const dim3 grid((unsigned)(B * tiles(cnn::conv_tx(32))), 1u);
+        hipLaunchKernelGGL(cnn::k_conv3x3<32>, grid, dim3(CONV_NT), 0, st, in, Wg, Kp, bias, res, res32, out16,
+                           out32, B, cin, cout, h, w, relu ? 1 : 0);
+    } else {
+        const dim3 grid((unsigned)(B * tiles(cnn::conv_tx(64))), (unsigned)((cout + 63) / 64));
+        hipLaunchKernelGGL(cnn::k_conv3x3<64>, grid, dim3(CONV_NT), 0, st, in, Wg, Kp, bias, res, res32, out16,
+                           out32, B, cin, cout, h, w, relu ? 1 : 0);
+    }
+}
 
 void conv_fwd(radon_cnn_s& c, const Conv& L, const uint16_t* in, int h, int w, uint16_t* out16, float* out32,
               const uint16_t* res, bool relu, hipStream_t st, const float* res32 = nullptr) {
-    const long long np = (long long)c.B * h * w;
-    const dim3 grid((unsigned)((np + 63) / 64), (unsigned)((L.cout + 63) / 64));
-    hipLaunchKernelGGL(cnn::k_conv3x3, grid, dim3(CONV_NT), 0, st, in, L.Wg, L.Kp, L.b, res, res32, out16, out32,
-                       c.B, L.cin, L.cout, h, w, relu ? 1 : 0);
+    conv_launch(in, L.Wg, L.Kp, L.b, res, res32, out16, out32, c.B, L.cin, L.cout, h, w, relu, st);
 }
 
 // data gradient: gin = conv(gout, flipped transposed kernel), no bias
 void conv_dgrad(radon_cnn_s& c, const Conv& L, const uint16_t* gout, int h, int w, uint16_t* gin, hipStream_t st) {
-    const long long np = (long long)c.B * h * w;
-    const dim3 grid((unsigned)((np + 63) / 64), (unsigned)((L.cin + 63) / 64));
-    hipLaunchKernelGGL(cnn::k_conv3x3, grid, dim3(CONV_NT), 0, st, gout, L.Wt, L.Kpt, nullptr, nullptr, nullptr,
-                       gin, nullptr, c.B, L.cout, L.cin, h, w, 0);
+    conv_launch(gout, L.Wt, L.Kpt, nullptr, nullptr, nullptr, gin, nullptr, c.B, L.cout, L.cin, h, w, false, st);
 }
 
 void conv_wgrad(radon_cnn_s& c, Conv& L, const uint16_t* gout, const uint16_t* in, int h, int w, hipStream_t st) {
     const long long np = (long long)c.B * h * w;
-    const int chunks = (int)((np + cnn::WG_CHUNK - 1) / cnn::WG_CHUNK);
+    const int chunks = (int)wgrad_chunks(c.B, h, w);
     const int K = L.cin * 9;
-    const dim3 grid((unsigned)chunks, (unsigned)((K + 31) / 32), (unsigned)((L.cout + 31) / 32));
-    hipLaunchKernelGGL(cnn::k_conv3x3_wgrad, grid, dim3(64), 0, st, gout, in, c.part, c.B, L.cin, L.cout, h, w);
+    const dim3 grid((unsigned)chunks, (unsigned)((K + 63) / 64), (unsigned)((L.cout + 63) / 64));
+    hipLaunchKernelGGL(cnn::k_conv3x3_wgrad, grid, dim3(256), 0, st, gout, in, c.part, c.B, L.cin, L.cout, h, w);
     hipLaunchKernelGGL(cnn::k_sum_chunks, dim3((unsigned)grid1(L.nw())), dim3(256), 0, st, c.part, chunks, L.nw(),
                        L.gw);
     // the bias partials reuse the weight partials' buffer, which the sum above has read
@@ -276,8 +292,7 @@ radon_status_t radon_cnn_create(radon_cnn_t* out, int batch, int height, int wid
         for (float* p : {L.mw, L.vw}) c->chk(hipMemcpy(p, z.data(), sizeof(float) * nw, hipMemcpyHostToDevice));
         for (float* p : {L.mb, L.vb}) c->chk(hipMemcpy(p, zb.data(), sizeof(float) * L.cout, hipMemcpyHostToDevice));
         pack(L, 0);
-        const size_t np = (size_t)batch * (height / sizes[l]) * (width / sizes[l]);
-        const size_t chunks = (np + cnn::WG_CHUNK - 1) / cnn::WG_CHUNK;
+        const size_t chunks = wgrad_chunks(batch, height / sizes[l], width / sizes[l]);
         part_n = std::max(part_n, chunks * nw);
     }
     const size_t s0 = (size_t)batch * height * width, s1 = s0 / 4, s2 = s0 / 16, s3 = s0 / 64;
@@ -412,8 +427,7 @@ radon_status_t radon_cnn_conv_test(const uint16_t* in, const float* w, const flo
     L.b = const_cast<float*>(bias);
     L.gw = gw;
     L.gb = gb;
-    const long long np = (long long)B * H * W;
-    const size_t chunks = (np + cnn::WG_CHUNK - 1) / cnn::WG_CHUNK;
+    const size_t chunks = wgrad_chunks(B, H, W);
     if (!c.alloc(&L.Wg, (size_t)Cout * L.Kp) || !c.alloc(&L.Wt, (size_t)Cin * L.Kpt) ||
         !c.alloc(&c.part, chunks * L.nw()))
         return errf(RADON_ERR_OOM, "test buffers");

@@ -27,7 +27,7 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-constexpr int CONV_NT = 256;   // 4 waves: a 64 x 64 output block (2 x 2 waves of 32 x 32)
+constexpr int CONV_NT = 256;   // 4 waves of 32 x 32 output blocks
 
 // Implicit-GEMM 3x3 convolution, stride 1, zero padding 1.
 //   out[b, co, y, x] = epilogue( sum_{ci, ky, kx} Wg[co][ci*9 + ky*3 + kx] *
@@ -36,59 +36,94 @@ constexpr int CONV_NT = 256;   // 4 waves: a 64 x 64 output block (2 x 2 waves o
 // Epilogue: + bias[co] (bias may be null), ReLU if relu, + res[b, co, y, x]
 // (res may be null, bf16) + res32[b, co, y, x] (may be null, float32).
 // Output bf16 (out16) and/or float32 (out32).
-// Grid: x = pixel blocks of 64 (over B*H*W), y = channel blocks of 64.
+// A workgroup takes CB output channels (64, or 32 for layers with at most 32)
+// and a TX x 8 pixel tile of one image (TX = 8 for CB = 64, 16 for CB = 32,
+// so that the 4 waves cover CB x TX * 8 outputs in 32 x 32 blocks): wave w
+// computes channel group w / NPG and pixel group w % NPG (32 consecutive
+// pixels of the tile in row order). The reduction runs over chunks of CK
+// input channels (CK * 9 = 72 values of K): the chunk's (TX + 2) x 10 input
+// window (zero outside the image and past Cin) and its CB x 72 weight slice
+// are staged in LDS, and each wave then takes 9 MFMAs with both operands read
+// from LDS. Grid: x = B * tiles, y = channel blocks of CB.
+constexpr int CK = 8;            // input channels per chunk
+constexpr int CKK = CK * 9;      // values of K per chunk
+constexpr int WP = CKK + 4;      // LDS pitch of a weight row in bf16 (8-byte aligned rows)
+constexpr int CTY = 8;           // pixel tile height
+constexpr int conv_tx(int cb) { return cb == 64 ? 8 : 16; }   // pixel tile width
+
+// LDS offset of value k of a chunk (channel k / 9, tap k % 9) in a window of
+// width WW, relative to the lane's pixel
+__device__ constexpr int xoff(int k, int WW) { return (k / 9) * WW * (CTY + 2) + ((k % 9) / 3) * WW + (k % 3); }
+
+template <int CB>
 __global__ __launch_bounds__(CONV_NT) void k_conv3x3(const uint16_t* __restrict__ in,
                                                     const uint16_t* __restrict__ Wg, int Kp,
                                                     const float* __restrict__ bias, const uint16_t* __restrict__ res,
                                                     const float* __restrict__ res32,
                                                     uint16_t* __restrict__ out16, float* __restrict__ out32,
                                                     int B, int Cin, int Cout, int H, int W, int relu) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int HW = H * W;
-    const long long NP = (long long)B * HW;
-    const int co0 = blockIdx.y * 64 + (wave >> 1) * 32;
-    const long long p0 = (long long)blockIdx.x * 64 + (wave & 1) * 32;
+    static_assert(CB == 64 || CB == 32, "channel blocks of 64 or 32");
+    constexpr int TX = conv_tx(CB), WW = TX + 2, WIN = WW * (CTY + 2);
+    constexpr int NPG = 4 / (CB / 32);   // pixel groups (waves per channel group)
+    __shared__ __align__(16) uint16_t wl[CB * WP];
+    __shared__ uint16_t xl[CK * WIN];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (W + TX - 1) / TX, tiles = tiles_x * ((H + CTY - 1) / CTY);
+    const int b = blockIdx.x / tiles;
+    const int tr = blockIdx.x - b * tiles;
+    const int ty0 = (tr / tiles_x) * CTY, tx0 = (tr - (tr / tiles_x) * tiles_x) * TX;
+    const int cb = blockIdx.y * CB;
     const int i = lane & 31, kh = lane >> 5;
-    // this lane's B column: pixel p0 + i
-    const long long p = p0 + i;
-    const bool pv = p < NP;
-    const int pb = pv ? (int)(p / HW) : 0;
-    const int prem = pv ? (int)(p - (long long)pb * HW) : 0;
-    const int py = prem / W, px = prem - (prem / W) * W;
-    const uint16_t* inb = in + (size_t)pb * Cin * HW;
-    // this lane's A row: output channel co0 + i
-    const int coA = co0 + i;
-    const bool av = coA < Cout;
-    const uint16_t* wrow = Wg + (size_t)(av ? coA : 0) * Kp;
-    const int K = Cin * 9;
+    const int cg = wave / NPG, pg = wave - cg * NPG;
+    const int arow = cg * 32 + i;                       // this lane's A row in the block
+    const int pl = pg * 32 + i;                         // this lane's B column: tile pixel pl
+    const int py = pl / TX, px = pl - (pl / TX) * TX;
+    const int pbase = py * WW + px;
+    const int HW = H * W;
+    const uint16_t* inb = in + (size_t)b * Cin * HW;
     f32x16 acc = {};
-    for (int k0 = 0; k0 < Kp; k0 += 8) {
-        bf16x4 a, b;
-        const int kb = k0 + 4 * kh;
-        if (av) {
-            const uint2 w2 = *reinterpret_cast<const uint2*>(wrow + kb);
+    for (int c0 = 0; c0 < Cin; c0 += CK) {
+        // weights: rows cb .. cb + CB - 1, K values c0 * 9 .. + 71, 8 at a time
+        // (c0 * 9 and Kp are multiples of 8, so a group lies wholly below Kp
+        // or wholly past it; past it belongs to the next row and reads as 0)
+        for (int e = tid; e < CB * (CKK / 8); e += CONV_NT) {
+            const int row = e / (CKK / 8), g8 = e - row * (CKK / 8);
+            const int co = cb + row, k = c0 * 9 + 8 * g8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (co < Cout && k < Kp) v = *reinterpret_cast<const uint4*>(Wg + (size_t)co * Kp + k);
+            uint2* d = reinterpret_cast<uint2*>(&wl[row * WP + 8 * g8]);
+            d[0] = make_uint2(v.x, v.y);
+            d[1] = make_uint2(v.z, v.w);
+        }
+        // input window: channels c0 .. c0 + CK - 1, rows ty0 - 1 .., columns tx0 - 1 ..
+        for (int e = tid; e < CK * WIN; e += CONV_NT) {
+            const int cl = e / WIN, rem = e - cl * WIN;
+            const int wy = rem / WW, wx = rem - (rem / WW) * WW;
+            const int ci = c0 + cl, yy = ty0 + wy - 1, xx = tx0 + wx - 1;
+            xl[e] = (ci < Cin && yy >= 0 && yy < H && xx >= 0 && xx < W) ? inb[(size_t)ci * HW + yy * W + xx] : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < CKK / 8; ++s) {
+            bf16x4 a, bv;
+            const uint2 w2 = *reinterpret_cast<const uint2*>(&wl[arow * WP + s * 8 + 4 * kh]);
             a[0] = (short)(w2.x & 0xffff);
             a[1] = (short)(w2.x >> 16);
             a[2] = (short)(w2.y & 0xffff);
             a[3] = (short)(w2.y >> 16);
-        } else {
-            a[0] = a[1] = a[2] = a[3] = 0;
-        }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int k = kb + t;
-            uint16_t v = 0;
-            if (pv && k < K) {
-                const int ci = k / 9, tap = k - (k / 9) * 9;
-                const int yy = py + tap / 3 - 1, xx = px + (tap - (tap / 3) * 3) - 1;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = inb[(size_t)ci * HW + yy * W + xx];
+            for (int t = 0; t < 4; ++t) {
+                const int o = kh ? xoff(s * 8 + 4 + t, WW) : xoff(s * 8 + t, WW);
+                bv[t] = (short)xl[pbase + o];
             }
-            b[t] = (short)v;
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        __syncthreads();
     }
-    // epilogue: lane holds column p0 + i, rows co0 + 8(r/4) + 4 kh + r%4
-    if (!pv) return;
+    // epilogue: lane holds tile pixel pl, rows (channels) 8(r/4) + 4 kh + r%4 of its group's 32
+    const int gy = ty0 + py, gx = tx0 + px;
+    if (gy >= H || gx >= W) return;
+    const int co0 = cb + cg * 32;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int co = co0 + 8 * (r >> 2) + 4 * kh + (r & 3);
@@ -96,7 +131,7 @@ __global__ __launch_bounds__(CONV_NT) void k_conv3x3(const uint16_t* __restrict_
         float v = acc[r];
         if (bias) v += bias[co];
         if (relu) v = fmaxf(v, 0.f);
-        const size_t o = ((size_t)pb * Cout + co) * HW + prem;
+        const size_t o = ((size_t)b * Cout + co) * HW + (size_t)gy * W + gx;
         if (res) v += bf2f(res[o]);
         if (res32) v += res32[o];
         if (out16) out16[o] = f2bf(v);
@@ -104,57 +139,95 @@ __global__ __launch_bounds__(CONV_NT) void k_conv3x3(const uint16_t* __restrict_
     }
 }
 
-// Weight gradient of the 3x3 convolution, split over pixel chunks:
+// Weight gradient of the 3x3 convolution, split over chunks of pixel tiles:
 //   part[chunk][co][k] = sum over the chunk's pixels p of
 //                        g[b, co, p] * in[b, ci(k), p + tap(k)]
-// (M = Cout, N = K = Cin*9, reduction over pixels); the chunks are summed in
-// order by k_sum_chunks. A wave computes a 32 (co) x 32 (k) block; the
-// reduction index runs over 8 pixels per MFMA. Grid: x = chunks, y = k blocks
-// of 32, z = co blocks of 32 (one wave per workgroup).
-constexpr int WG_CHUNK = 4096;   // pixels per chunk (a multiple of 8)
-
-__global__ __launch_bounds__(64) void k_conv3x3_wgrad(const uint16_t* __restrict__ g,
-                                                     const uint16_t* __restrict__ in, float* __restrict__ part,
-                                                     int B, int Cin, int Cout, int H, int W) {
-    const int lane = threadIdx.x;
-    const int HW = H * W;
-    const long long NP = (long long)B * HW;
-    const int K = Cin * 9;
+// (M = Cout, N = K = Cin*9, the reduction over pixels, 8 per MFMA). A
+// workgroup takes 64 channels x 64 values of K and WT_TILES 8 x 8 pixel
+// tiles (image by image, tiles in row order); for each tile the gradient
+// block (64 channels x 64 pixels, zero outside the image) and the 10 x 10
+// input window of the (at most 8) channels the K block reaches are staged in
+// LDS, and each wave takes 8 MFMAs (one per tile row) with both operands read
+// from LDS; wave w computes channels 32 (w >> 1) .. and values of K
+// 32 (w & 1) .. of the block. The tiles are taken in order, so the partial
+// sums are deterministic; the chunks are summed in order by k_sum_chunks.
+// Grid: x = chunks, y = K blocks of 64, z = channel blocks of 64.
+constexpr int WT_TILES = 64;          // 8 x 8 tiles per chunk
+constexpr int GP = 64 + 4;            // LDS pitch of a gradient row in bf16 (8-byte aligned rows)
+constexpr int WCH = 8;                // channels a K block of 64 reaches: (k0 % 9 + 63) / 9 + 1 <= 8
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const uint16_t* __restrict__ g,
+                                                      const uint16_t* __restrict__ in, float* __restrict__ part,
+                                                      int B, int Cin, int Cout, int H, int W) {
+    __shared__ __align__(16) uint16_t gl[64 * GP];
+    __shared__ uint16_t xl[WCH * 100];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 31, kh = lane >> 5;
-    const int coA = blockIdx.z * 32 + i;     // A row
-    const int kB = blockIdx.y * 32 + i;      // B column
-    const bool av = coA < Cout, bv = kB < K;
-    const int ci = bv ? kB / 9 : 0, tap = bv ? kB - (kB / 9) * 9 : 0;
-    const int dy = tap / 3 - 1, dx = tap - (tap / 3) * 3 - 1;
-    const long long c0 = (long long)blockIdx.x * WG_CHUNK;
+    const int tiles_x = (W + 7) / 8, tiles = tiles_x * ((H + 7) / 8);
+    const long long ntiles = (long long)B * tiles;
+    const int K = Cin * 9;
+    const int kb0 = blockIdx.y * 64, cb = blockIdx.z * 64;
+    const int ci0 = kb0 / 9;                               // first channel of the window
+    const int arow = (wave >> 1) * 32 + i;                 // A row: channel cb + arow
+    const int kcol = kb0 + (wave & 1) * 32 + i;            // B column: value kcol of K
+    const bool kv = kcol < K;
+    const int kci = kv ? kcol / 9 - ci0 : 0, ktap = kv ? kcol - (kcol / 9) * 9 : 0;
+    const int koff = kci * 100 + (ktap / 3) * 10 + (ktap - (ktap / 3) * 3);   // window offset of tile pixel (0, 0)
     f32x16 acc = {};
-    for (int s = 0; s < WG_CHUNK; s += 8) {
-        bf16x4 a, b;
+    const long long t0 = (long long)blockIdx.x * WT_TILES;
+    for (int tt = 0; tt < WT_TILES; ++tt) {
+        const long long t = t0 + tt;
+        if (t >= ntiles) break;   // uniform
+        const int b = (int)(t / tiles), tr = (int)(t - (long long)b * tiles);
+        const int ty0 = (tr / tiles_x) * 8, tx0 = (tr - (tr / tiles_x) * tiles_x) * 8;
+        // gradient block: channel rows, 8 pixels of one tile row per step
+        for (int e = tid; e < 64 * 8; e += 256) {
+            const int row = e >> 3, r8 = e & 7;
+            const int co = cb + row, yy = ty0 + r8;
+            uint4 q = make_uint4(0u, 0u, 0u, 0u);
+            if (co < Cout && yy < H) {
+                const uint16_t* src = g + ((size_t)(b * Cout + co) * H + yy) * W + tx0;
+                if (W % 8 == 0) {
+                    q = *reinterpret_cast<const uint4*>(src);
+                } else {
+                    uint16_t v[8];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const long long p = c0 + s + 4 * kh + t;
-            uint16_t va = 0, vb = 0;
-            if (p < NP) {
-                const int pb = (int)(p / HW);
-                const int prem = (int)(p - (long long)pb * HW);
-                if (av) va = g[((size_t)pb * Cout + coA) * HW + prem];
-                if (bv) {
-                    const int py = prem / W, px = prem - (prem / W) * W;
-                    const int yy = py + dy, xx = px + dx;
-                    if (yy >= 0 && yy < H && xx >= 0 && xx < W) vb = in[((size_t)pb * Cin + ci) * HW + yy * W + xx];
+                    for (int j = 0; j < 8; ++j) v[j] = (tx0 + j < W) ? src[j] : 0;
+                    q = make_uint4(v[0] | ((unsigned)v[1] << 16), v[2] | ((unsigned)v[3] << 16),
+                                   v[4] | ((unsigned)v[5] << 16), v[6] | ((unsigned)v[7] << 16));
                 }
             }
-            a[t] = (short)va;
-            b[t] = (short)vb;
+            uint2* d = reinterpret_cast<uint2*>(&gl[row * GP + r8 * 8]);
+            d[0] = make_uint2(q.x, q.y);
+            d[1] = make_uint2(q.z, q.w);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        // input window of channels ci0 .. ci0 + WCH - 1
+        for (int e = tid; e < WCH * 100; e += 256) {
+            const int cl = e / 100, rem = e - cl * 100, wy = rem / 10, wx = rem - (rem / 10) * 10;
+            const int ci = ci0 + cl, yy = ty0 + wy - 1, xx = tx0 + wx - 1;
+            xl[e] = (ci < Cin && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                        ? in[((size_t)(b * Cin + ci) * H + yy) * W + xx] : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {   // tile row s: pixels 8 s + 4 kh + t
+            bf16x4 a, bv;
+            const uint2 w2 = *reinterpret_cast<const uint2*>(&gl[arow * GP + s * 8 + 4 * kh]);
+            a[0] = (short)(w2.x & 0xffff);
+            a[1] = (short)(w2.x >> 16);
+            a[2] = (short)(w2.y & 0xffff);
+            a[3] = (short)(w2.y >> 16);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bv[t] = kv ? (short)xl[koff + s * 10 + 4 * kh + t] : (short)0;
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+        }
+        __syncthreads();
     }
     float* dst = part + (size_t)blockIdx.x * Cout * K;
-    if (!bv) return;
+    if (!kv) return;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int co = blockIdx.z * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-        if (co < Cout) dst[(size_t)co * K + kB] = acc[r];
+        const int co = cb + (wave >> 1) * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        if (co < Cout) dst[(size_t)co * K + kcol] = acc[r];
     }
 }
 
