@@ -81,7 +81,7 @@ hipError_t launch_a3(const Plan& p, hipStream_t st) {
 }
 
 hipError_t launch_a4(const Plan& p, float* img, hipStream_t st) {
-    const dim3 grid((p.n + 3) / 4);
+    const dim3 grid(row_blocks(p.n));
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \

@@ -7,7 +7,7 @@
 namespace rn {
 
 hipError_t launch_f1(const Plan& p, const float* img, hipStream_t st) {
-    const dim3 grid((p.n + 3) / 4);
+    const dim3 grid(row_blocks(p.n));
     switch (p.n) {
 #define RN_CASE(L)                                                                             \
     case L: {                                                                                  \
@@ -161,12 +161,12 @@ PassSlice pass_slice_of(const Plan& p, PassKind kind, const void* in, void* out)
     e.shift = p.shift_n;
     e.wq = nullptr;
     switch (kind) {
-        case PK_F1: e.nblk = (p.n + 3) / 4; e.in = in; e.out = p.T1; e.tw = p.tw_n; break;
+        case PK_F1: e.nblk = row_blocks(p.n); e.in = in; e.out = p.T1; e.tw = p.tw_n; break;
         case PK_F2: e.nblk = p.n + 1; e.in = p.T1; e.out = p.grid; e.tw = p.tw_n; break;
         case PK_F4: e.nblk = (p.n_views + 1) / 2; e.in = p.Xr; e.out = out; e.tw = p.tw_N; break;
         case PK_A1: e.nblk = (p.n_views + 1) / 2; e.in = in; e.out = p.Yh; e.tw = p.tw_N; break;
         case PK_A3: e.nblk = p.n + 1; e.in = p.grid; e.out = p.T1; e.tw = p.tw_n; break;
-        case PK_A4: e.nblk = (p.n + 3) / 4; e.in = p.T1; e.out = out; e.tw = p.tw_n; break;
+        case PK_A4: e.nblk = row_blocks(p.n); e.in = p.T1; e.out = out; e.tw = p.tw_n; break;
     }
     return e;
 }

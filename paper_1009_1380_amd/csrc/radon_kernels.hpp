@@ -117,24 +117,35 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // ---------------------------------------------------------------- F1
-// Four image rows per workgroup, packed as two complex lines z_p = row 2p +
-// i row 2p+1 (p = 0, 1). Row i holds py = i - n/2, column j holds px = j - n/2
-// (stored at px mod n in the length-n FFT). The even frequencies mx = 2k are
-// the length-n FFT of z_p, the odd ones mx = 2k+1 that of z_p e^{-i pi px/n};
-// the two line pairs are transformed one after the other, and each
-// frequency's four outputs are written to T1[mx][i0..i0+3] (32 contiguous
-// bytes) straight from LDS. Only the deapodized inputs wait in registers.
-// Waves per SIMD the row kernels are compiled for: with 1024 threads, 8
-// holds two workgroups on a CU (at most 64 VGPRs per lane), which lines of up
-// to 2560 points fit without spilling.
-constexpr int row_waves(int len) { return len <= 2560 ? 8 : 4; }
+// 2 NLN image rows per workgroup, packed as NLN complex lines z_p = row 2p +
+// i row 2p+1. Row i holds py = i - n/2, column j holds px = j - n/2 (stored
+// at px mod n in the length-n FFT). The even frequencies mx = 2k are the
+// length-n FFT of z_p, the odd ones mx = 2k+1 that of z_p e^{-i pi px/n};
+// the lines are transformed together for the even frequencies, then for the
+// odd ones, and each frequency's 2 NLN outputs are written to
+// T1[mx][i0..i0+2NLN-1] (16 NLN contiguous bytes) straight from LDS. Only the
+// deapodized inputs wait in registers.
+//
+// Complex lines per workgroup (row_lines): 2 (four rows), or n/512 for
+// n = 2048 and 2560, so that the n rows form one round of one workgroup per
+// CU (256 CUs; the 84 or 106 KB of LDS lines admit one workgroup per CU).
+// With two lines, 2560 rows make 640 workgroups, two resident per CU, and a
+// fifth of them ran in a second round.
+constexpr int row_lines(int len) { return (len == 2048 || len == 2560) ? len / 512 : 2; }
+// Waves per SIMD the row kernels are compiled for: with 1024 threads and two
+// lines, 8 holds two workgroups on a CU (at most 64 VGPRs per lane), which
+// lines of up to 2560 points fit without spilling; one workgroup per CU
+// needs 4.
+constexpr int row_waves(int len) { return row_lines(len) > 2 ? 4 : (len <= 2560 ? 8 : 4); }
+// workgroups of a row pass over n rows
+constexpr int row_blocks(int n) { return (n + 2 * row_lines(n) - 1) / (2 * row_lines(n)); }
 
 template <int NL, int NT>
 __device__ __forceinline__ void f1_store(float2* __restrict__ T1, const float2* lds, int m, int k, int kc, int i0,
                                          int p) {
-    // line p gives rows i0 + 2p and i0 + 2p + 1 (16 bytes); the lanes of a pair
-    // take p = 0 and 1 of one frequency, so one store instruction fills 32 whole
-    // 32-byte pieces
+    // line p gives rows i0 + 2p and i0 + 2p + 1 (16 bytes); consecutive lanes
+    // take the lines p = 0 .. NLN-1 of one frequency, so one store instruction
+    // fills whole 16 NLN-byte pieces
     constexpr int LS = lds_ls(NL);
     const float2 zk = lds[p * LS + lds_pad(k)];
     const float2 zc = cconj(lds[p * LS + lds_pad(kc)]);
@@ -151,22 +162,23 @@ __device__ __forceinline__ void f1_body(int bid_, int nblk_, const float* __rest
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
     constexpr int LS = lds_ls(NL);
+    constexpr int NLN = row_lines(NL);
     constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
-    __shared__ float2 lds[2 * LS];
+    __shared__ float2 lds[NLN * LS];
     const int tid = threadIdx.x;
-    const int i0 = 4 * xcd_block(bid_, nblk_);
-    float2 z[PJ][2];
+    const int i0 = 2 * NLN * xcd_block(bid_, nblk_);
+    float2 z[PJ][NLN];
 #pragma unroll
     for (int c = 0; c < PJ; ++c) {
         const int j = tid + c * NT;
-        float r[4];
+        float r[2 * NLN];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) r[q] = (j < NL && i0 + q < NL) ? img[(size_t)(i0 + q) * NL + j] : 0.f;
+        for (int q = 0; q < 2 * NLN; ++q) r[q] = (j < NL && i0 + q < NL) ? img[(size_t)(i0 + q) * NL + j] : 0.f;
         if (j < NL) {
             const float pj = psi_inv[j];
             const int pos = lds_pad((j + NL / 2) % NL);
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+            for (int p = 0; p < NLN; ++p) {
                 const int r0 = i0 + 2 * p;
                 const float sa = r0 < NL ? psi_inv[r0] : 0.f;
                 const float sb = r0 + 1 < NL ? psi_inv[r0 + 1] : 0.f;
@@ -176,10 +188,10 @@ __device__ __forceinline__ void f1_body(int bid_, int nblk_, const float* __rest
         }
     }
     lds_sync();
-    fft_lds<NL, 2, NT>(lds, tw, tid);
-    for (int e = tid; e < 2 * (NL / 2 + 1); e += NT) {
-        const int k = e >> 1;
-        f1_store<NL, NT>(T1, lds, 2 * k, k, (NL - k) % NL, i0, e & 1);
+    fft_lds<NL, NLN, NT>(lds, tw, tid);
+    for (int e = tid; e < NLN * (NL / 2 + 1); e += NT) {
+        const int k = e / NLN;
+        f1_store<NL, NT>(T1, lds, 2 * k, k, (NL - k) % NL, i0, e - k * NLN);
     }
     lds_sync();
 #pragma unroll
@@ -189,14 +201,14 @@ __device__ __forceinline__ void f1_body(int bid_, int nblk_, const float* __rest
             const int pos = lds_pad((j + NL / 2) % NL);
             const float2 sh = shift[j];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) lds[p * LS + pos] = cmul(z[c][p], sh);
+            for (int p = 0; p < NLN; ++p) lds[p * LS + pos] = cmul(z[c][p], sh);
         }
     }
     lds_sync();
-    fft_lds<NL, 2, NT>(lds, tw, tid);
-    for (int e = tid; e < 2 * (NL / 2); e += NT) {
-        const int k = e >> 1;
-        f1_store<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e & 1);
+    fft_lds<NL, NLN, NT>(lds, tw, tid);
+    for (int e = tid; e < NLN * (NL / 2); e += NT) {
+        const int k = e / NLN;
+        f1_store<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e - k * NLN);
     }
 }
 
@@ -922,20 +934,21 @@ __device__ __forceinline__ void a3_body(int bid_, int nblk_, const float2* __res
 }
 
 // ---------------------------------------------------------------- A4
-// Four image rows per workgroup: complex-to-real inverse FFT along mx of
-// T1[mx][i], mx = 0..n (Hermitian extension to G points), keep px =
-// -n/2..n/2-1, deapodize. Rows 2p and 2p+1 are packed as one complex line
-// (X_2p + i X_{2p+1}); its even positions mx = 2k form the length-n line E_p
-// and its odd ones the line O_p, and the pixel is E_p(px) + e^{+i pi px/n}
-// O_p(px). The E lines of both pairs are transformed first (their results
-// wait in registers), then the O lines; each T1[mx][i0..i0+3] (32 contiguous
-// bytes) is read once, by the pass of its parity.
+// 2 NLN image rows per workgroup (NLN = row_lines(n), as in F1):
+// complex-to-real inverse FFT along mx of T1[mx][i], mx = 0..n (Hermitian
+// extension to G points), keep px = -n/2..n/2-1, deapodize. Rows 2p and 2p+1
+// are packed as one complex line (X_2p + i X_{2p+1}); its even positions
+// mx = 2k form the length-n line E_p and its odd ones the line O_p, and the
+// pixel is E_p(px) + e^{+i pi px/n} O_p(px). The E lines are transformed
+// first (their results wait in registers), then the O lines; each
+// T1[mx][i0..i0+2NLN-1] (16 NLN contiguous bytes) is read once, by the pass
+// of its parity.
 template <int NL, int NT>
 __device__ __forceinline__ void a4_load(const float2* __restrict__ T1, float2* lds, int m, int pk, int pc, int i0,
                                         int p) {
-    // line p takes rows i0 + 2p and i0 + 2p + 1 (16 bytes); the lanes of a pair
-    // take p = 0 and 1 of one frequency, so one load instruction reads 32 whole
-    // 32-byte pieces
+    // line p takes rows i0 + 2p and i0 + 2p + 1 (16 bytes); consecutive lanes
+    // take the lines p = 0 .. NLN-1 of one frequency, so one load instruction
+    // reads whole 16 NLN-byte pieces
     constexpr int LS = lds_ls(NL);
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (i0 + 2 * p + 1 < NL) v = *reinterpret_cast<const float4*>(T1 + (size_t)m * NL + i0 + 2 * p);
@@ -955,35 +968,36 @@ __device__ __forceinline__ void a4_body(int bid_, int nblk_, const float2* __res
                                                const float2* __restrict__ shift,
                                                const float2* __restrict__ tw) {
     constexpr int LS = lds_ls(NL);
+    constexpr int NLN = row_lines(NL);
     constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
-    __shared__ float2 lds[2 * LS];
+    __shared__ float2 lds[NLN * LS];
     const int tid = threadIdx.x;
-    const int i0 = 4 * xcd_block(bid_, nblk_);
+    const int i0 = 2 * NLN * xcd_block(bid_, nblk_);
     // even mx = 2k: position k, mirror 2n - 2k at n - k
-    for (int e = tid; e < 2 * (NL / 2 + 1); e += NT) {
-        const int k = e >> 1;
-        a4_load<NL, NT>(T1, lds, 2 * k, k, NL - k, i0, e & 1);
+    for (int e = tid; e < NLN * (NL / 2 + 1); e += NT) {
+        const int k = e / NLN;
+        a4_load<NL, NT>(T1, lds, 2 * k, k, NL - k, i0, e - k * NLN);
     }
     lds_sync();
-    fft_lds<NL, 2, NT>(lds, tw, tid);
-    float2 e[PJ][2];
+    fft_lds<NL, NLN, NT>(lds, tw, tid);
+    float2 e[PJ][NLN];
 #pragma unroll
     for (int c = 0; c < PJ; ++c) {
         const int j = tid + c * NT;
         if (j < NL) {
             const int pos = lds_pad((j + NL / 2) % NL);
 #pragma unroll
-            for (int p = 0; p < 2; ++p) e[c][p] = cconj(lds[p * LS + pos]);
+            for (int p = 0; p < NLN; ++p) e[c][p] = cconj(lds[p * LS + pos]);
         }
     }
     lds_sync();
     // odd mx = 2k+1: position k, mirror 2n - 2k - 1 at n - 1 - k
-    for (int e = tid; e < 2 * (NL / 2); e += NT) {
-        const int k = e >> 1;
-        a4_load<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e & 1);
+    for (int e2 = tid; e2 < NLN * (NL / 2); e2 += NT) {
+        const int k = e2 / NLN;
+        a4_load<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e2 - k * NLN);
     }
     lds_sync();
-    fft_lds<NL, 2, NT>(lds, tw, tid);
+    fft_lds<NL, NLN, NT>(lds, tw, tid);
 #pragma unroll
     for (int c = 0; c < PJ; ++c) {
         const int j = tid + c * NT;
@@ -992,7 +1006,7 @@ __device__ __forceinline__ void a4_body(int bid_, int nblk_, const float2* __res
             const float2 sh = cconj(shift[j]);
             const float pj = psi_inv[j];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+            for (int p = 0; p < NLN; ++p) {
                 const float2 o = cconj(lds[p * LS + pos]);
                 const float2 zz = cadd(e[c][p], cmul(sh, o));
                 const int r0 = i0 + 2 * p;
