@@ -27,7 +27,7 @@ hipError_t launch_a1(const Plan& p, const float* sino, bool filtered, hipStream_
 template <int W, int T>
 static hipError_t launch_a2_wt(const Plan& p, hipStream_t st) {
     if (p.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_a2_spread<W, T>), dim3(p.n_items), dim3(A2_NT), 0, st, p.items, p.offs4,
+    hipLaunchKernelGGL((k_a2_spread<W, T>), dim3(p.n_items), dim3(A2_NT), 0, st, p.items,
                        p.recs, p.Yh, p.kbc, p.grid, p.partials, p.G);
     return hipGetLastError();
 }

@@ -367,6 +367,23 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
                 fitems.push_back({cx, cy, nbx, s, std::min(p.f3_chunk, n_all - s), 0, 0, 0});
         }
     }
+    // each item's visit ranges: the diagonal neighbour's class 2, the
+    // v-neighbours' classes 2-3, the u-neighbour's classes 1-2 and the own
+    // bins (consecutive bins, one range)
+    for (rn::TileItem& it : items) {
+        const int xl = (it.cx + ntl - 1) % ntl, yu = (it.cy + ntl - 1) % ntl;
+        auto range = [&](int q, int b0, int c0, int b1, int c1) {
+            it.rs[q] = o4[4 * b0 + c0];
+            it.rl[q] = o4[4 * b1 + c1] - it.rs[q];
+        };
+        range(0, yu * ntl + xl, 2, yu * ntl + xl, 3);
+        for (int j = 0; j < rn::A2_GX; ++j) {
+            if (j < it.gx) range(1 + j, yu * ntl + it.cx + j, 2, yu * ntl + it.cx + j, 4);
+            else it.rs[1 + j] = it.rl[1 + j] = 0;
+        }
+        range(rn::A2_GX + 1, it.cy * ntl + xl, 1, it.cy * ntl + xl, 3);
+        range(rn::A2_GX + 2, it.cy * ntl + it.cx, 0, it.cy * ntl + it.cx + it.gx, 0);
+    }
     // longest items first so the tail of each launch is short
     std::stable_sort(items.begin(), items.end(),
                      [](const rn::TileItem& a, const rn::TileItem& b) { return a.count > b.count; });

@@ -332,15 +332,25 @@ __device__ __forceinline__ int footprint_origin(int b, int W, int G) { return wr
 // straddling mx = 0 are taken whole.
 __device__ __forceinline__ bool forward_column(int cx, int ntl) { return cx == 0 || cx >= ntl / 2 - 1; }
 
-// Forward / spreading work item: a slice of the sorted samples of one tile.
+#ifndef RN_A2_GX
+#define RN_A2_GX 2
+#endif
+constexpr int A2_GX = RN_A2_GX;   // tile columns per strip (at most)
+constexpr int A2_NR = A2_GX + 3;  // visit ranges of a strip
+
+// Spreading work item: a slice of the visit list of one output strip. The
+// list is the concatenation of A2_NR ranges of the sorted samples (start rs,
+// length rl), taken from the bin offsets when the plan is built, so that the
+// kernel reads them with the item instead of looking them up after it.
 struct TileItem {
-    int cx, cy;      // tile, centred tile coordinates
-    int start;       // first position (forward: absolute in perm; spreading: visit index)
-    int count;       // number of samples / visits
-    int slot;        // spreading only: -1 writes the grid, else partial slot
-    int gx;          // spreading only: tile columns of the strip
+    int cx, cy;      // first tile of the strip, centred tile coordinates
+    int start;       // first visit of the slice in the strip's list
+    int count;       // number of visits
+    int slot;        // -1 writes the grid, else partial slot
+    int gx;          // tile columns of the strip
     int plan;        // batches: index of the item's plan in the batch (else 0)
     int pad;
+    int rs[A2_NR], rl[A2_NR];
 };
 
 // Per-sample record in sorted order, built once per plan so that the
@@ -645,16 +655,12 @@ __device__ __forceinline__ void a1_body(int bid_, int nblk_, const float* __rest
 #ifndef RN_A2_CHUNK
 #define RN_A2_CHUNK 512
 #endif
-#ifndef RN_A2_GX
-#define RN_A2_GX 2
-#endif
 constexpr int A2_NT = RN_A2_NT;
 constexpr int A2_CHUNK = RN_A2_CHUNK;
 // the fixed-point scale below keeps every sum of at most 512 contributions
 // inside int32
 static_assert(A2_CHUNK <= 512, "A2 items hold at most 512 visits");
 constexpr int A2_VPT = (A2_CHUNK + A2_NT - 1) / A2_NT;
-constexpr int A2_GX = RN_A2_GX;   // tile columns per strip (at most)
 
 // Waves per SIMD the spreading kernel is compiled for when W <= 6 (at most
 // 80 VGPRs; W = 8 keeps its natural allocation).
@@ -662,20 +668,18 @@ constexpr int A2_GX = RN_A2_GX;   // tile columns per strip (at most)
 #define RN_A2_WPE 6
 #endif
 template <int W, int T>
-__device__ __forceinline__ void a2_item(const TileItem& it, const int* __restrict__ offs4,
-                                        const SampleRec* __restrict__ recs, const float2* __restrict__ Yh,
+__device__ __forceinline__ void a2_item(const TileItem& it, const SampleRec* __restrict__ recs, const float2* __restrict__ Yh,
                                         const float4* __restrict__ kbc, float2* __restrict__ grid,
                                         float2* __restrict__ partials, int G) {
     constexpr int PX = A2_GX * T + 2 * (W - 1);   // accumulator: local [-(W-1), A2_GX T + W-1) along u
     constexpr int PY = T + 2 * (W - 1);           // and [-(W-1), T + W-1) along v
     constexpr int NKB = (W / 2) * KB_S;
-    constexpr int NR = A2_GX + 3;                 // visit ranges
+    constexpr int NR = A2_NR;                     // visit ranges
     __shared__ __align__(16) unsigned long long acc[PX * PY];
     __shared__ float4 kbt[NKB];
     __shared__ float wmax[A2_NT / 64];
     const int tid = threadIdx.x;
     const int gx = it.gx;
-    const int ntl = G / T;
 
     // T is even, so PX * PY is: clear the accumulator 16 bytes at a time
     static_assert(T % 2 == 0 && (PX * PY) % 2 == 0, "accumulator cleared in pairs of words");
@@ -683,28 +687,13 @@ __device__ __forceinline__ void a2_item(const TileItem& it, const int* __restric
     for (int e = tid; e < NKB; e += A2_NT) kbt[e] = kbc[e];
     lds_sync();
 
-    // visit ranges: diagonal class 2, v-neighbours classes 2-3, u-neighbour
-    // classes 1-2, own bins (consecutive bins, one range)
-    const int xl = (it.cx + ntl - 1) % ntl, yu = (it.cy + ntl - 1) % ntl;
+    // visit ranges (diagonal class 2, v-neighbours classes 2-3, u-neighbour
+    // classes 1-2, own bins), from the item
     int rs[NR], rl[NR];
-    {
-        const int b = yu * ntl + xl;
-        rs[0] = offs4[4 * b + 2];
-        rl[0] = offs4[4 * b + 3] - rs[0];
-    }
 #pragma unroll
-    for (int j = 0; j < A2_GX; ++j) {
-        const int b = yu * ntl + it.cx + j;
-        rs[1 + j] = j < gx ? offs4[4 * b + 2] : 0;
-        rl[1 + j] = j < gx ? offs4[4 * b + 4] - rs[1 + j] : 0;
-    }
-    {
-        const int b = it.cy * ntl + xl;
-        rs[A2_GX + 1] = offs4[4 * b + 1];
-        rl[A2_GX + 1] = offs4[4 * b + 3] - rs[A2_GX + 1];
-        const int bo = it.cy * ntl + it.cx;
-        rs[A2_GX + 2] = offs4[4 * bo];
-        rl[A2_GX + 2] = offs4[4 * (bo + gx)] - rs[A2_GX + 2];
+    for (int q = 0; q < NR; ++q) {
+        rs[q] = it.rs[q];
+        rl[q] = it.rl[q];
     }
     const int x0 = it.cx * T, y0 = it.cy * T;
 
@@ -1066,11 +1055,11 @@ __global__ __launch_bounds__(NT) void k_a1_rays(const float* __restrict__ sino, 
 
 template <int W, int T>
 __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_A2_WPE : 1))) void k_a2_spread(
-    const TileItem* __restrict__ items, const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
+    const TileItem* __restrict__ items, const SampleRec* __restrict__ recs,
     const float2* __restrict__ Yh, const float4* __restrict__ kbc, float2* __restrict__ grid,
     float2* __restrict__ partials, int G) {
     const TileItem it = items[blockIdx.x];
-    a2_item<W, T>(it, offs4, recs, Yh, kbc, grid, partials, G);
+    a2_item<W, T>(it, recs, Yh, kbc, grid, partials, G);
 }
 
 template <int T>

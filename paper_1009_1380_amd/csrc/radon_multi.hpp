@@ -119,7 +119,7 @@ __global__ __launch_bounds__(A2_NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? 
     const TileItem* __restrict__ items, const GridSlice* __restrict__ gs, const float4* __restrict__ kbc) {
     const TileItem it = items[blockIdx.x];
     const GridSlice g = gs[it.plan];
-    a2_item<W, T>(it, g.offs4, g.recs, g.Yh, kbc, g.grid, g.partials, g.G);
+    a2_item<W, T>(it, g.recs, g.Yh, kbc, g.grid, g.partials, g.G);
 }
 
 template <int T>
