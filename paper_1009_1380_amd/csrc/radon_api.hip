@@ -364,7 +364,7 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
                 n_all += run(cy * ntl + cx1, 0, 4) + run(cy1 * ntl + cx1, 0, 4);
             }
             for (int s = 0; s < n_all; s += p.f3_chunk)
-                fitems.push_back({cx, cy, nbx, s, std::min(p.f3_chunk, n_all - s), 0, 0, 0});
+                fitems.push_back({cx, cy, nbx, s, std::min(p.f3_chunk, n_all - s), 0, {}, {}, 0});
         }
     }
     // each item's visit ranges: the diagonal neighbour's class 2, the
@@ -383,6 +383,14 @@ radon_status_t build_work(Plan& p, const std::vector<int>& o4) {
         }
         range(rn::A2_GX + 1, it.cy * ntl + xl, 1, it.cy * ntl + xl, 3);
         range(rn::A2_GX + 2, it.cy * ntl + it.cx, 0, it.cy * ntl + it.cx + it.gx, 0);
+    }
+    // each forward item's bin ranges
+    for (rn::F3Item& it : fitems) {
+        const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
+        const int b[4] = {it.cy * ntl + it.cx, it.cy * ntl + cx1, cy1 * ntl + it.cx, cy1 * ntl + cx1};
+        for (int q = 0; q < 4; ++q) it.s[q] = o4[4 * b[q]];
+        for (int q = 0; q < 3; ++q) it.n[q] = o4[4 * b[q] + 4] - it.s[q];
+        if (it.nbx < 2) it.n[1] = 0;
     }
     // longest items first so the tail of each launch is short
     std::stable_sort(items.begin(), items.end(),

@@ -45,7 +45,7 @@ hipError_t launch_f2(const Plan& p, hipStream_t st) {
 template <int W, int T>
 static hipError_t launch_f3_wt(const Plan& p, hipStream_t st) {
     if (p.n_fitems == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_f3_tiles<W, T, 512>), dim3(p.f3_grid), dim3(512), 0, st, p.fitems, p.n_fitems, p.offs4,
+    hipLaunchKernelGGL((k_f3_tiles<W, T, 512>), dim3(p.f3_grid), dim3(512), 0, st, p.fitems, p.n_fitems,
                        p.recs, p.grid, p.kbc, p.Xr, p.G);
     return hipGetLastError();
 }
@@ -171,7 +171,7 @@ PassSlice pass_slice_of(const Plan& p, PassKind kind, const void* in, void* out)
     return e;
 }
 
-GridSlice grid_slice_of(const Plan& p) { return GridSlice{p.offs4, p.recs, p.grid, p.Xr, p.Yh, p.partials, p.G, 0}; }
+GridSlice grid_slice_of(const Plan& p) { return GridSlice{p.recs, p.grid, p.Xr, p.Yh, p.partials, p.G, 0}; }
 
 template <int W, int T>
 static hipError_t launch_f3m_wt(const GridLaunch& g, const GridSlice* gs, hipStream_t st) {

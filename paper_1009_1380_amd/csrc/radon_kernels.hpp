@@ -397,13 +397,19 @@ __device__ __forceinline__ SampleRec load_rec(const SampleRec* __restrict__ recs
 // is evaluated: q >= 0 when its origin tile is a forward column, else -q
 // (result conjugated); the pair (-N/2, +N/2) likewise. Results go to
 // Xr[a][t], t = |q| (t = N/2: Nyquist).
+//
+// The item carries the sorted-sample ranges of its bins (taken from the bin
+// offsets when the plan is built), so that its first records and its region
+// are requested right after the item itself.
 struct F3Item {
     int cx, cy;      // first bin of the super-tile, centred tile coordinates
     int nbx;         // bins of the super-tile along u that are forward columns (1 or 2)
     int start;       // first sample of the slice within the concatenated bins
     int count;       // samples in this slice
     int plan;        // batches: index of the item's plan in the batch (else 0)
-    int pad1, pad2;
+    int s[4];        // first sorted sample of bins (cx, cy), (cx+1, cy), (cx, cy+1), (cx+1, cy+1)
+    int n[3];        // samples of the first three (the second counts only when nbx = 2)
+    int pad;
 };
 
 // Persistent: workgroup b takes items b, b + gridDim.x, ... (the grid is the
@@ -418,21 +424,15 @@ constexpr int F3_CHUNK = 2048;   // samples per work item
 // One work item: stage the super-tile's region in `tile`, interpolate its
 // samples. `kbt` holds the kernel's cubic pieces in LDS.
 template <int W, int T, int NT>
-__device__ __forceinline__ void f3_item(const F3Item& it, const int* __restrict__ offs4,
-                                        const SampleRec* __restrict__ recs, const float2* __restrict__ grid,
+__device__ __forceinline__ void f3_item(const F3Item& it, const SampleRec* __restrict__ recs, const float2* __restrict__ grid,
                                         float2* __restrict__ Xr, int G, float2* tile, const float4* kbt, int tid) {
     constexpr int P = 2 * T + W - 1;
     constexpr int PP = P * P;
     constexpr int PE = (PP + NT - 1) / NT;            // staged points per thread
-    const int ntl = G / T;
     {
         const int x0 = it.cx * T, y0 = it.cy * T;
-        const int cx1 = (it.cx + 1) % ntl, cy1 = (it.cy + 1) % ntl;
-        const int b0 = it.cy * ntl + it.cx, b1 = it.cy * ntl + cx1, b2 = cy1 * ntl + it.cx, b3 = cy1 * ntl + cx1;
-        const int s0 = offs4[4 * b0], n0 = offs4[4 * b0 + 4] - s0;
-        const int s1 = offs4[4 * b1], n1 = (it.nbx > 1) ? offs4[4 * b1 + 4] - s1 : 0;
-        const int s2 = offs4[4 * b2], n2 = offs4[4 * b2 + 4] - s2;
-        const int s3 = offs4[4 * b3];
+        const int s0 = it.s[0], n0 = it.n[0], s1 = it.s[1], n1 = it.n[1];
+        const int s2 = it.s[2], n2 = it.n[2], s3 = it.s[3];
         auto position = [&](int k) {
             int u = it.start + k;
             if (u < n0) return s0 + u;
@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(NT) void k_f2_cols(const float2* __restrict__ T1, f
 // number of workgroups that fit on the device at once).
 template <int W, int T, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_F3_WPE : 1))) void k_f3_tiles(
-    const F3Item* __restrict__ items, int n_items, const int* __restrict__ offs4, const SampleRec* __restrict__ recs,
+    const F3Item* __restrict__ items, int n_items, const SampleRec* __restrict__ recs,
     const float2* __restrict__ grid, const float4* __restrict__ kbc, float2* __restrict__ Xr, int G) {
     constexpr int PP = (2 * T + W - 1) * (2 * T + W - 1);
     constexpr int NKB = (W / 2) * KB_S;
@@ -1036,7 +1036,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_
     for (int e = tid; e < NKB; e += NT) kbt[e] = kbc[e];
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const F3Item it = items[i];
-        f3_item<W, T, NT>(it, offs4, recs, grid, Xr, G, tile, kbt, tid);
+        f3_item<W, T, NT>(it, recs, grid, Xr, G, tile, kbt, tid);
     }
 }
 

@@ -86,7 +86,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(row_waves(NL
 
 // The gridding buffers of one slice.
 struct GridSlice {
-    const int* offs4;
     const SampleRec* recs;
     float2* grid;
     float2* Xr;          // forward: interpolated ray spectra
@@ -110,7 +109,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W <= 6 ? RN_
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const F3Item it = items[i];
         const GridSlice g = gs[it.plan];
-        f3_item<W, T, NT>(it, g.offs4, g.recs, g.grid, g.Xr, g.G, tile, kbt, tid);
+        f3_item<W, T, NT>(it, g.recs, g.grid, g.Xr, g.G, tile, kbt, tid);
     }
 }
 
