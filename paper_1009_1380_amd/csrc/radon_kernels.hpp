@@ -128,7 +128,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 //
 // Complex lines per workgroup (row_lines): 2 (four rows), or n/512 for
 // n = 2048 and 2560, so that the n rows form one round of one workgroup per
-// CU (256 CUs; the 84 or 106 KB of LDS lines admit one workgroup per CU).
+// CU (256 CUs; at 2560 the 106 KB of LDS lines, at 2048 the registers, admit
+// one workgroup per CU).
 // With two lines, 2560 rows make 640 workgroups, two resident per CU, and a
 // fifth of them ran in a second round.
 constexpr int row_lines(int len) { return (len == 2048 || len == 2560) ? len / 512 : 2; }
