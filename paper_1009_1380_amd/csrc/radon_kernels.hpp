@@ -164,52 +164,106 @@ __device__ __forceinline__ void f1_body(int bid_, int nblk_, const float* __rest
                                                const float2* __restrict__ tw) {
     constexpr int LS = lds_ls(NL);
     constexpr int NLN = row_lines(NL);
-    constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
     __shared__ float2 lds[NLN * LS];
     const int tid = threadIdx.x;
     const int i0 = 2 * NLN * xcd_block(bid_, nblk_);
-    float2 z[PJ][NLN];
+    using IO = FftRegIO<NL, NLN, NT>;
+    if constexpr (IO::NP >= 2) {
+        // The deapodized inputs are loaded straight into the first butterflies:
+        // butterfly b = tid + it NT (line b / NB0) takes FFT positions
+        // q = bf + m NB0, which hold pixel j = (q + n/2) mod n of rows
+        // i0 + 2 line and i0 + 2 line + 1. They wait in z for the odd pass.
+        float2 z[IO::IT0][IO::R0], v[IO::IT0][IO::R0];
 #pragma unroll
-    for (int c = 0; c < PJ; ++c) {
-        const int j = tid + c * NT;
-        float r[2 * NLN];
+        for (int it = 0; it < IO::IT0; ++it) {
+            const int b = tid + it * NT;
+            const int line = b / IO::NB0, bf = b - line * IO::NB0;
+            const int r0 = i0 + 2 * line;
+            const bool ok = b < IO::NB0 * NLN;
+            const bool oka = ok && r0 < NL, okb = ok && r0 + 1 < NL;
+            const float sa = oka ? psi_inv[r0] : 0.f;
+            const float sb = okb ? psi_inv[r0 + 1] : 0.f;
 #pragma unroll
-        for (int q = 0; q < 2 * NLN; ++q) r[q] = (j < NL && i0 + q < NL) ? img[(size_t)(i0 + q) * NL + j] : 0.f;
-        if (j < NL) {
-            const float pj = psi_inv[j];
-            const int pos = lds_pad((j + NL / 2) % NL);
-#pragma unroll
-            for (int p = 0; p < NLN; ++p) {
-                const int r0 = i0 + 2 * p;
-                const float sa = r0 < NL ? psi_inv[r0] : 0.f;
-                const float sb = r0 + 1 < NL ? psi_inv[r0 + 1] : 0.f;
-                z[c][p] = make_float2(r[2 * p] * sa * pj, r[2 * p + 1] * sb * pj);
-                lds[p * LS + pos] = z[c][p];
+            for (int m = 0; m < IO::R0; ++m) {
+                const int j = (bf + m * IO::NB0 + NL / 2) % NL;
+                const float ra = oka ? img[(size_t)r0 * NL + j] : 0.f;
+                const float rb = okb ? img[(size_t)(r0 + 1) * NL + j] : 0.f;
+                const float pj = ok ? psi_inv[j] : 0.f;
+                z[it][m] = make_float2(ra * sa * pj, rb * sb * pj);
+                v[it][m] = z[it][m];
             }
         }
-    }
-    lds_sync();
-    fft_lds<NL, NLN, NT>(lds, tw, tid);
-    for (int e = tid; e < NLN * (NL / 2 + 1); e += NT) {
-        const int k = e / NLN;
-        f1_store<NL, NT>(T1, lds, 2 * k, k, (NL - k) % NL, i0, e - k * NLN);
-    }
-    lds_sync();
-#pragma unroll
-    for (int c = 0; c < PJ; ++c) {
-        const int j = tid + c * NT;
-        if (j < NL) {
-            const int pos = lds_pad((j + NL / 2) % NL);
-            const float2 sh = shift[j];
-#pragma unroll
-            for (int p = 0; p < NLN; ++p) lds[p * LS + pos] = cmul(z[c][p], sh);
+        fft_first_from_regs<NL, NLN, NT>(v, lds, tid);
+        lds_sync();
+        fft_passes<NL, 1, IO::R0, NLN, NT, LS>(lds, tw, tid);
+        for (int e = tid; e < NLN * (NL / 2 + 1); e += NT) {
+            const int k = e / NLN;
+            f1_store<NL, NT>(T1, lds, 2 * k, k, (NL - k) % NL, i0, e - k * NLN);
         }
-    }
-    lds_sync();
-    fft_lds<NL, NLN, NT>(lds, tw, tid);
-    for (int e = tid; e < NLN * (NL / 2); e += NT) {
-        const int k = e / NLN;
-        f1_store<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e - k * NLN);
+        lds_sync();
+#pragma unroll
+        for (int it = 0; it < IO::IT0; ++it) {
+            const int b = tid + it * NT;
+            const int line = b / IO::NB0, bf = b - line * IO::NB0;
+            const bool ok = b < IO::NB0 * NLN;
+#pragma unroll
+            for (int m = 0; m < IO::R0; ++m) {
+                const int j = (bf + m * IO::NB0 + NL / 2) % NL;
+                v[it][m] = ok ? cmul(z[it][m], shift[j]) : make_float2(0.f, 0.f);
+            }
+        }
+        fft_first_from_regs<NL, NLN, NT>(v, lds, tid);
+        lds_sync();
+        fft_passes<NL, 1, IO::R0, NLN, NT, LS>(lds, tw, tid);
+        for (int e = tid; e < NLN * (NL / 2); e += NT) {
+            const int k = e / NLN;
+            f1_store<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e - k * NLN);
+        }
+    } else {
+        constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
+        float2 z[PJ][NLN];
+#pragma unroll
+        for (int c = 0; c < PJ; ++c) {
+            const int j = tid + c * NT;
+            float r[2 * NLN];
+#pragma unroll
+            for (int q = 0; q < 2 * NLN; ++q) r[q] = (j < NL && i0 + q < NL) ? img[(size_t)(i0 + q) * NL + j] : 0.f;
+            if (j < NL) {
+                const float pj = psi_inv[j];
+                const int pos = lds_pad((j + NL / 2) % NL);
+#pragma unroll
+                for (int p = 0; p < NLN; ++p) {
+                    const int r0 = i0 + 2 * p;
+                    const float sa = r0 < NL ? psi_inv[r0] : 0.f;
+                    const float sb = r0 + 1 < NL ? psi_inv[r0 + 1] : 0.f;
+                    z[c][p] = make_float2(r[2 * p] * sa * pj, r[2 * p + 1] * sb * pj);
+                    lds[p * LS + pos] = z[c][p];
+                }
+            }
+        }
+        lds_sync();
+        fft_lds<NL, NLN, NT>(lds, tw, tid);
+        for (int e = tid; e < NLN * (NL / 2 + 1); e += NT) {
+            const int k = e / NLN;
+            f1_store<NL, NT>(T1, lds, 2 * k, k, (NL - k) % NL, i0, e - k * NLN);
+        }
+        lds_sync();
+#pragma unroll
+        for (int c = 0; c < PJ; ++c) {
+            const int j = tid + c * NT;
+            if (j < NL) {
+                const int pos = lds_pad((j + NL / 2) % NL);
+                const float2 sh = shift[j];
+#pragma unroll
+                for (int p = 0; p < NLN; ++p) lds[p * LS + pos] = cmul(z[c][p], sh);
+            }
+        }
+        lds_sync();
+        fft_lds<NL, NLN, NT>(lds, tw, tid);
+        for (int e = tid; e < NLN * (NL / 2); e += NT) {
+            const int k = e / NLN;
+            f1_store<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e - k * NLN);
+        }
     }
 }
 
@@ -959,49 +1013,91 @@ __device__ __forceinline__ void a4_body(int bid_, int nblk_, const float2* __res
                                                const float2* __restrict__ tw) {
     constexpr int LS = lds_ls(NL);
     constexpr int NLN = row_lines(NL);
-    constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
     __shared__ float2 lds[NLN * LS];
     const int tid = threadIdx.x;
     const int i0 = 2 * NLN * xcd_block(bid_, nblk_);
-    // even mx = 2k: position k, mirror 2n - 2k at n - k
-    for (int e = tid; e < NLN * (NL / 2 + 1); e += NT) {
-        const int k = e / NLN;
-        a4_load<NL, NT>(T1, lds, 2 * k, k, NL - k, i0, e - k * NLN);
-    }
-    lds_sync();
-    fft_lds<NL, NLN, NT>(lds, tw, tid);
-    float2 e[PJ][NLN];
-#pragma unroll
-    for (int c = 0; c < PJ; ++c) {
-        const int j = tid + c * NT;
-        if (j < NL) {
-            const int pos = lds_pad((j + NL / 2) % NL);
-#pragma unroll
-            for (int p = 0; p < NLN; ++p) e[c][p] = cconj(lds[p * LS + pos]);
+    using IO = FftRegIO<NL, NLN, NT>;
+    if constexpr (IO::NP >= 2) {
+        // Both transforms leave their last pass in registers: butterfly
+        // b = tid + it NT (line b / NBL) holds FFT positions q = bf + m NBL,
+        // pixel j = (q + n/2) mod n of rows i0 + 2 line and i0 + 2 line + 1.
+        float2 E[IO::ITL][IO::RL], O[IO::ITL][IO::RL];
+        // even mx = 2k: position k, mirror 2n - 2k at n - k
+        for (int e = tid; e < NLN * (NL / 2 + 1); e += NT) {
+            const int k = e / NLN;
+            a4_load<NL, NT>(T1, lds, 2 * k, k, NL - k, i0, e - k * NLN);
         }
-    }
-    lds_sync();
-    // odd mx = 2k+1: position k, mirror 2n - 2k - 1 at n - 1 - k
-    for (int e2 = tid; e2 < NLN * (NL / 2); e2 += NT) {
-        const int k = e2 / NLN;
-        a4_load<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e2 - k * NLN);
-    }
-    lds_sync();
-    fft_lds<NL, NLN, NT>(lds, tw, tid);
+        lds_sync();
+        fft_mid_passes<NL, 0, 1, NLN, NT, LS>(lds, tw, tid);
+        fft_last_to_regs<NL, NLN, NT>(lds, tw, tid, E);
+        lds_sync();   // the last pass read the lines
+        // odd mx = 2k+1: position k, mirror 2n - 2k - 1 at n - 1 - k
+        for (int e = tid; e < NLN * (NL / 2); e += NT) {
+            const int k = e / NLN;
+            a4_load<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e - k * NLN);
+        }
+        lds_sync();
+        fft_mid_passes<NL, 0, 1, NLN, NT, LS>(lds, tw, tid);
+        fft_last_to_regs<NL, NLN, NT>(lds, tw, tid, O);
 #pragma unroll
-    for (int c = 0; c < PJ; ++c) {
-        const int j = tid + c * NT;
-        if (j < NL) {
-            const int pos = lds_pad((j + NL / 2) % NL);
-            const float2 sh = cconj(shift[j]);
-            const float pj = psi_inv[j];
+        for (int it = 0; it < IO::ITL; ++it) {
+            const int b = tid + it * NT;
+            if (b < IO::NBL * NLN) {
+                const int line = b / IO::NBL, bf = b - line * IO::NBL;
+                const int r0 = i0 + 2 * line;
 #pragma unroll
-            for (int p = 0; p < NLN; ++p) {
-                const float2 o = cconj(lds[p * LS + pos]);
-                const float2 zz = cadd(e[c][p], cmul(sh, o));
-                const int r0 = i0 + 2 * p;
-                if (r0 < NL) img[(size_t)r0 * NL + j] = zz.x * psi_inv[r0] * pj;
-                if (r0 + 1 < NL) img[(size_t)(r0 + 1) * NL + j] = zz.y * psi_inv[r0 + 1] * pj;
+                for (int m = 0; m < IO::RL; ++m) {
+                    const int j = (bf + m * IO::NBL + NL / 2) % NL;
+                    const float2 sh = cconj(shift[j]);
+                    const float pj = psi_inv[j];
+                    const float2 zz = cadd(cconj(E[it][m]), cmul(sh, cconj(O[it][m])));
+                    if (r0 < NL) img[(size_t)r0 * NL + j] = zz.x * psi_inv[r0] * pj;
+                    if (r0 + 1 < NL) img[(size_t)(r0 + 1) * NL + j] = zz.y * psi_inv[r0 + 1] * pj;
+                }
+            }
+        }
+    } else {
+        constexpr int PJ = (NL + NT - 1) / NT;       // pixels px per thread and row
+        // even mx = 2k: position k, mirror 2n - 2k at n - k
+        for (int e = tid; e < NLN * (NL / 2 + 1); e += NT) {
+            const int k = e / NLN;
+            a4_load<NL, NT>(T1, lds, 2 * k, k, NL - k, i0, e - k * NLN);
+        }
+        lds_sync();
+        fft_lds<NL, NLN, NT>(lds, tw, tid);
+        float2 e[PJ][NLN];
+#pragma unroll
+        for (int c = 0; c < PJ; ++c) {
+            const int j = tid + c * NT;
+            if (j < NL) {
+                const int pos = lds_pad((j + NL / 2) % NL);
+#pragma unroll
+                for (int p = 0; p < NLN; ++p) e[c][p] = cconj(lds[p * LS + pos]);
+            }
+        }
+        lds_sync();
+        // odd mx = 2k+1: position k, mirror 2n - 2k - 1 at n - 1 - k
+        for (int e2 = tid; e2 < NLN * (NL / 2); e2 += NT) {
+            const int k = e2 / NLN;
+            a4_load<NL, NT>(T1, lds, 2 * k + 1, k, NL - 1 - k, i0, e2 - k * NLN);
+        }
+        lds_sync();
+        fft_lds<NL, NLN, NT>(lds, tw, tid);
+#pragma unroll
+        for (int c = 0; c < PJ; ++c) {
+            const int j = tid + c * NT;
+            if (j < NL) {
+                const int pos = lds_pad((j + NL / 2) % NL);
+                const float2 sh = cconj(shift[j]);
+                const float pj = psi_inv[j];
+#pragma unroll
+                for (int p = 0; p < NLN; ++p) {
+                    const float2 o = cconj(lds[p * LS + pos]);
+                    const float2 zz = cadd(e[c][p], cmul(sh, o));
+                    const int r0 = i0 + 2 * p;
+                    if (r0 < NL) img[(size_t)r0 * NL + j] = zz.x * psi_inv[r0] * pj;
+                    if (r0 + 1 < NL) img[(size_t)(r0 + 1) * NL + j] = zz.y * psi_inv[r0 + 1] * pj;
+                }
             }
         }
     }
