@@ -315,6 +315,26 @@ def test_full_size_slice_vs_oracle():
     assert ea < TOL_GRID
 
 
+@pytest.mark.parametrize("n", [1536, 2048])
+def test_large_sizes_vs_oracle(n):
+    """The row passes' workgroup shapes at the other large sizes (2048: eight
+    rows per workgroup, one round; 1536: four rows): forward and adjoint of an
+    n^2 disk phantom at 90 views x n bins against O-grid (FP64)."""
+    from radon_inputs import config2_phantom
+    note(f"large size n={n}: phantom + plan")
+    nv = 90
+    x = config2_phantom(3, n)
+    ang = uniform_angles(nv)
+    plan = Plan(n, ang, n)
+    y = plan.forward(to_dev(x)).cpu().numpy()
+    a = plan.adjoint(to_dev(y)).cpu().numpy()
+    note(f"large size n={n}: oracle")
+    ey = rel(y, grid_forward(x.astype(np.float64), ang, n))
+    ea = rel(a, grid_adjoint(y.astype(np.float64), ang, n))
+    note(f"large size n={n}: forward {ey:.3e}, adjoint {ea:.3e}")
+    assert ey < TOL_GRID and ea < TOL_GRID
+
+
 def test_full_size_gaussian_closed_form():
     """G5 at full size: no O(n^2 M) work, closed-form projections."""
     note("full size gaussian")
