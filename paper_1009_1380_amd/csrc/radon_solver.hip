@@ -238,9 +238,11 @@ __global__ __launch_bounds__(SV_NT) void k_sv_bb(const float* __restrict__ x, co
 // S(lam) = sum max(|v| - lam, 0) = tau. S is continuous, decreasing and
 // piecewise linear with breakpoints at the values |v_i|, so the root is found
 // exactly by locating it between two consecutive values: a radix select on the
-// bit pattern u of |v| (monotone in |v| for non-negative floats), 12 + 12 + 7
-// bits in three levels. Each level histograms the elements whose leading bits
-// match the bin chosen so far, by count and by the exact integer sum of their
+// bit pattern u of |v| (monotone in |v| for non-negative floats), 12 + 10 + 9
+// bits in three levels (a narrower second level makes the merge of its
+// histograms into global memory and the decision after it cheaper than with
+// 12 + 12 + 7). Each level histograms the elements whose leading bits match
+// the bin chosen so far, by count and by the exact integer sum of their
 // significands (the bins of a level share one exponent), so the histograms are
 // order-independent integers and the select is deterministic. From the counts
 // and sums above each bin edge e, S(e) is exact up to the final float64 sums;
@@ -261,8 +263,13 @@ constexpr int PJ_NT = 256;
 #define RN_PJ_BLOCKS 256
 #endif
 constexpr int PJ_BLOCKS = RN_PJ_BLOCKS;
-constexpr int PJ_BINS = 4096;    // bins of levels 1 and 2 (12 bits each)
-constexpr int PJ_BINS3 = 128;    // bins of level 3 (7 bits: one float value each)
+#ifndef RN_PJ_B2
+#define RN_PJ_B2 10
+#endif
+constexpr int PJ_B1 = 12, PJ_B2 = RN_PJ_B2, PJ_B3 = 31 - PJ_B1 - PJ_B2;   // bits of the three levels
+constexpr int PJ_BINS = 4096;            // histogram capacity of levels 1 and 2 (at most 12 bits)
+constexpr int PJ_BINS3 = 1 << PJ_B3;     // bins of level 3 (one float value each)
+static_assert(PJ_B2 <= 12 && PJ_B3 >= 1 && PJ_B3 <= 12, "level widths");
 
 // Decision after a level: the threshold (done), or the bin to refine (the
 // leading bits of u fixed so far) with the sum and count of |v| above it.
@@ -283,12 +290,13 @@ struct PjWork {
 
 template <int L>
 struct PjLevel {
-    static constexpr int NB = L == 3 ? PJ_BINS3 : PJ_BINS;
-    static constexpr int SHIFT = L == 1 ? 19 : L == 2 ? 7 : 0;   // digit = (u >> SHIFT) % NB
-    static constexpr int PSHIFT = SHIFT + (L == 3 ? 7 : 12);      // u >> PSHIFT must equal the prefix
+    static constexpr int BITS = L == 1 ? PJ_B1 : L == 2 ? PJ_B2 : PJ_B3;
+    static constexpr int NB = 1 << BITS;
+    static constexpr int SHIFT = L == 1 ? 31 - PJ_B1 : L == 2 ? 31 - PJ_B1 - PJ_B2 : 0;   // digit = (u >> SHIFT) % NB
+    static constexpr int PSHIFT = SHIFT + BITS;   // u >> PSHIFT must equal the prefix
     // bit pattern of the lower edge of bin b (b = NB carries into the prefix)
     __device__ static unsigned edge(unsigned prefix, unsigned b) {
-        return L == 1 ? b << 19 : L == 2 ? (prefix << 19) + (b << 7) : (prefix << 7) + b;
+        return L == 1 ? b << SHIFT : (prefix << PSHIFT) + (b << SHIFT);
     }
 };
 
@@ -410,7 +418,7 @@ __device__ PjState pj_decide(const unsigned* __restrict__ hcnt, const unsigned l
             d.done = 0.0;
             d.A = dV;
             d.C = dC;
-            d.prefix = L == 1 ? (unsigned)bstar : (prefix << 12) | (unsigned)bstar;
+            d.prefix = L == 1 ? (unsigned)bstar : (prefix << Lv::BITS) | (unsigned)bstar;
         }
         out = d;
     }
@@ -451,9 +459,11 @@ __global__ __launch_bounds__(PJ_NT) void k_sv_pj_pass(const float* __restrict__ 
     unsigned prefix = 0u;
     if (L == 1) {
         // the level-3 histogram was read by the last soft threshold: clear it
-        if (blockIdx.x == 0 && threadIdx.x < PJ_BINS3) {
-            w.cnt3[threadIdx.x] = 0u;
-            w.sum3[threadIdx.x] = 0ull;
+        if (blockIdx.x == 0) {
+            for (int b = threadIdx.x; b < PJ_BINS3; b += PJ_NT) {
+                w.cnt3[b] = 0u;
+                w.sum3[b] = 0ull;
+            }
         }
     } else {
         PjState up{0.0, 0.0, 0.0, 0.0, 0u, 0u};
