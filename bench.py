@@ -8,7 +8,7 @@ bins, oversampling 2, Kaiser-Bessel width 6. The value is sinogram samples
 through one forward+adjoint pair per second (Gsamples/s), inputs resident in
 HBM. Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 30] [--warmup 5]
+    python bench.py [--gpus 1] [--steps 30] [--warmup 200]
 
 Only one GPU is used; --gpus above 1 exits with a message.
 """
@@ -296,10 +296,12 @@ def batch_times(dev, n_slices: int = 64, repeats: int = 5, seed: int = 0, tune: 
     return out
 
 
-def warmstart_times(pairs: int = 256, epochs: int = 4, n_eval: int = 20):
+def warmstart_times(pairs: int = 1024, epochs: int = 6, n_eval: int = 40):
     """Learned warm start on the 512^2, 90-view workload, reduced so the bench
     stays short (the full 2000-pair run is paper_1009_1380_amd.warmstart):
-    pairs generated by the method, training, cold vs warm on held-out seeds."""
+    pairs generated by the method, training, cold vs warm on held-out seeds.
+    About 26 s on one MI355X; with 256 pairs, 4 epochs and 20 slices (8 s) the
+    median warm/cold ratio moved between 0.81 and 0.96 from run to run."""
     import torch
 
     from paper_1009_1380_amd import WarmStartNet
