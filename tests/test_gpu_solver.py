@@ -118,7 +118,9 @@ def test_reduced_view_solve_full_size():
     xw, sw = plan.solve_bpdn(bd, sigma, x0=plan.fbp(bd), opt_tol=1e-3, max_iter=5000)
     note(f"warm {sw}")
     assert sw["status"] == 2 and abs(sw["rnorm"] - sigma) <= 2e-3 * sigma
-    assert abs(sw["x_l1"] - sc["x_l1"]) <= 2e-2 * sc["x_l1"]
+    # both stop where | ||r|| - sigma | <= 1e-3 ||r||, i.e. at inexact points of
+    # the Pareto curve; measured 1.5e-3 apart (930573 cold, 929208 warm)
+    assert abs(sw["x_l1"] - sc["x_l1"]) <= 5e-3 * sc["x_l1"]
 
 
 def _fallback_problem():
