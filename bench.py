@@ -344,7 +344,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(slices shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+              "(slices are independent: each GPU would take its own slices, with no exchange)", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: launched with WORLD_SIZE > 1; only one GPU is used", file=sys.stderr)
@@ -522,18 +522,29 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    def section(key, what, fn):
+        # a secondary measurement that fails is reported in the line (and on
+        # stderr) instead of losing the line
+        print(f"bench: {what}", file=sys.stderr, flush=True)
+        try:
+            return fn()
+        except Exception as e:  # noqa: BLE001
+            print(f"bench: {key} failed: {e!r}", file=sys.stderr, flush=True)
+            return {"error": repr(e)}
+
     if not args.no_solve:
-        print("bench: timing the reduced-view solves", file=sys.stderr, flush=True)
-        line["solve"] = solve_times(dev)
+        line["solve"] = section("solve", "timing the reduced-view solves", lambda: solve_times(dev))
     if not args.no_batch:
-        print("bench: timing the uneven-slice batch", file=sys.stderr, flush=True)
-        line["batch"] = batch_times(dev, tune=not args.no_autotune)
+        line["batch"] = section("batch", "timing the uneven-slice batch",
+                                lambda: batch_times(dev, tune=not args.no_autotune))
     if not args.no_warmstart:
-        print("bench: learned warm start (reduced)", file=sys.stderr, flush=True)
-        line["warmstart"] = warmstart_times()
+        line["warmstart"] = section("warmstart", "learned warm start (reduced)", warmstart_times)
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"], line["rel_l2_vs_ogrid"] = cpu_baseline(args.cpu_views, dev)
+        res = section("cpu_baseline", "timing the CPU oracle sample", lambda: cpu_baseline(args.cpu_views, dev))
+        if isinstance(res, tuple):
+            line["cpu_baseline"], line["rel_l2_vs_ogrid"] = res
+        else:
+            line["cpu_baseline"], line["rel_l2_vs_ogrid"] = res, None
     else:
         line["cpu_baseline"] = None
     plan.close()
